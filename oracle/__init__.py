@@ -1,0 +1,185 @@
+"""FP64 CPU oracle for the HISQ even-odd CG -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The HIP library never does, and this
+package never loads the HIP library: the two share no code.
+
+``hisq_oracle.c`` holds the arithmetic (HISQ Dslash of eq. (3) of Kaczmarek et
+al., GPUHEP2014, the even-odd operator A = 4m^2 - D_eo D_oe, CG, the link force
+and the 14-real Naik encoding); this module only compiles it with gcc and
+marshals numpy arrays through ctypes.  ``oracle.dense`` assembles the same
+operator as a dense matrix for tiny lattices.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hisq_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CONVERGED, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile hisq_oracle.c into liboracle.so (plain -O2, no fast-math)."""
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=gnu99", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB_PATH)
+            P = ctypes.c_void_p
+            I = ctypes.c_int
+            D = ctypes.c_double
+            Lp = ctypes.POINTER(ctypes.c_int)
+            lib.orc_dslash_full.argtypes = [Lp, I, P, P, P, P]
+            lib.orc_dslash_eo.argtypes = [Lp, I, I, P, P, P, P]
+            lib.orc_apply_A.argtypes = [Lp, I, D, P, P, P, P]
+            lib.orc_cg.argtypes = [Lp, I, D, P, P, P, P, D, I, P, P, P, P]
+            lib.orc_residual.argtypes = [Lp, I, D, P, P, P, P, P]
+            lib.orc_force.argtypes = [Lp, I, D, P, P, P, P, P, P, P]
+            lib.orc_r14_pack.argtypes = [ctypes.c_long, P, P, P]
+            lib.orc_r14_unpack.argtypes = [ctypes.c_long, P, P]
+            lib.orc_num_threads.argtypes = []
+            _lib = lib
+    return _lib
+
+
+def _geom(L):
+    L = [int(v) for v in L]
+    if len(L) != 4:
+        raise ValueError("lattice must have 4 extents")
+    return (ctypes.c_int * 4)(*L)
+
+
+def _c128(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None and a.shape != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), a.shape))
+    return a
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _check(rc):
+    if rc < 0:
+        raise ValueError("oracle call failed with code %d" % rc)
+    return rc
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def _links(L, U, N):
+    V = int(np.prod(L))
+    return _c128(U, (4, V, 3, 3)), _c128(N, (4, V, 3, 3))
+
+
+def dslash_full(L, U, N, v):
+    """w = D v on the full lattice; v is (V, 3, n)."""
+    U, N = _links(L, U, N)
+    v = _c128(v)
+    w = np.empty_like(v)
+    _check(_load().orc_dslash_full(_geom(L), v.shape[2], _ptr(U), _ptr(N), _ptr(v), _ptr(w)))
+    return w
+
+
+def dslash_eo(L, U, N, v, out_parity):
+    """Half-lattice Dslash: input parity 1-out_parity, output parity out_parity."""
+    U, N = _links(L, U, N)
+    v = _c128(v)
+    w = np.empty_like(v)
+    _check(_load().orc_dslash_eo(_geom(L), v.shape[2], int(out_parity), _ptr(U), _ptr(N),
+                                 _ptr(v), _ptr(w)))
+    return w
+
+
+def apply_A(L, U, N, m, x):
+    """y = (4 m^2 - D_eo D_oe) x on an even half field (V/2, 3, n)."""
+    U, N = _links(L, U, N)
+    x = _c128(x)
+    y = np.empty_like(x)
+    _check(_load().orc_apply_A(_geom(L), x.shape[2], float(m), _ptr(U), _ptr(N), _ptr(x), _ptr(y)))
+    return y
+
+
+def cg(L, U, N, m, b, tol=1e-13, maxiter=20000, x0=None):
+    """Plain FP64 CG per rhs; returns (x, info)."""
+    U, N = _links(L, U, N)
+    b = _c128(b)
+    n = b.shape[2]
+    x = np.zeros_like(b) if x0 is None else _c128(x0).copy()
+    iters = np.zeros(n, dtype=np.int32)
+    tres = np.zeros(n)
+    ires = np.zeros(n)
+    status = np.zeros(n, dtype=np.int32)
+    _check(_load().orc_cg(_geom(L), n, float(m), _ptr(U), _ptr(N), _ptr(b), _ptr(x), float(tol),
+                          int(maxiter), _ptr(iters), _ptr(tres), _ptr(ires), _ptr(status)))
+    return x, {"iters": iters, "true_res": tres, "iter_res": ires, "status": status}
+
+
+def residual(L, U, N, m, b, x):
+    """||b_k - A x_k|| / ||b_k|| per rhs, in FP64."""
+    U, N = _links(L, U, N)
+    b = _c128(b)
+    x = _c128(x, b.shape)
+    rel = np.zeros(b.shape[2])
+    _check(_load().orc_residual(_geom(L), b.shape[2], float(m), _ptr(U), _ptr(N), _ptr(b),
+                                _ptr(x), _ptr(rel)))
+    return rel
+
+
+def force(L, U, N, m, x, y):
+    """(G_U, G_N, dL/dm) for L = sum_k Re(phi_k^dag x_k), given x and y = A^{-1} phi."""
+    U, N = _links(L, U, N)
+    x = _c128(x)
+    y = _c128(y, x.shape)
+    GU = np.empty_like(U)
+    GN = np.empty_like(N)
+    dm = np.zeros(1)
+    _check(_load().orc_force(_geom(L), x.shape[2], float(m), _ptr(U), _ptr(N), _ptr(x), _ptr(y),
+                             _ptr(GU), _ptr(GN), _ptr(dm)))
+    return GU, GN, float(dm[0])
+
+
+def r14_pack(M):
+    """Compress (..., 3, 3) complex matrices to (..., 14) reals; returns (packed, max_err)."""
+    M = _c128(M)
+    lead = M.shape[:-2]
+    count = int(np.prod(lead)) if lead else 1
+    out = np.empty(lead + (14,), dtype=np.float64)
+    err = np.zeros(1)
+    _check(_load().orc_r14_pack(count, _ptr(M), _ptr(out), _ptr(err)))
+    return out, float(err[0])
+
+
+def r14_unpack(P):
+    """Inverse of r14_pack."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    lead = P.shape[:-1]
+    count = int(np.prod(lead)) if lead else 1
+    M = np.empty(lead + (3, 3), dtype=np.complex128)
+    _check(_load().orc_r14_unpack(count, _ptr(P), _ptr(M)))
+    return M
