@@ -1,0 +1,236 @@
+"""Benchmark: HISQ Dslash GB/s and CG time-to-solution on one MI355X.
+
+Workload: 48^3 x 12 lattice, 8 bundled rhs, m = 0.01, links drawn with
+smearing width 0.2 (synthetic stand-in for the finite-temperature gauge
+ensembles the paper measures on), complex Gaussian sources.
+
+One step = one mixed-precision (FP32 iteration, FP64 reliable updates) CG solve
+of the 8-rhs bundle with r14 Naik links, from x = 0 to true residual 1e-10;
+inputs and packed links are resident in HBM before the timed region.  Every
+Dslash launch inside the timed steps is timed with HIP events on the stream it
+runs on.
+
+The JSON line reports
+  value          algorithmic GB/s of the two half-Dslash kernels of the CG
+                 (links + one read of the input + one write/update of outputs),
+  roofline       the dominant kernel's achieved GB/s against 8 TB/s,
+  cg             time-to-solution of the step against 8 sequential FP64 1-rhs
+                 solves of the same sources (same GPU), iterations, residuals,
+  dslash_sweep   standalone Dslash GB/s for n = 1, 2, 4, 8 (FP64, FP32, r14),
+  cpu_baseline   the FP64 CPU oracle's Dslash on the host cores (a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GB/s (% HBM peak) at 1-8 rhs; CG solve time mixed vs FP64 @1e-10"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--lattice", type=str, default="48,48,48,12")
+    ap.add_argument("--nrhs", type=int, default=8)
+    ap.add_argument("--mass", type=float, default=0.01)
+    ap.add_argument("--eps", type=float, default=0.2)
+    ap.add_argument("--naik", choices=["r14", "full"], default="r14")
+    ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the solver shards by rhs bundle with no "
+              "communication, so --gpus %d is not run (use --gpus 1)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1411_4439_amd import hisq as H
+    from paper_1411_4439_amd import roofline as R
+    from paper_1411_4439_amd import workload as W
+
+    L = tuple(int(v) for v in args.lattice.split(","))
+    n, m = args.nrhs, args.mass
+    naik = H.NAIK_R14 if args.naik == "r14" else H.NAIK_FULL
+    Vh = W.half_volume(L)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    t0 = time.time()
+    U, N = W.make_links(L, args.eps, W.links_seed(3))
+    b = W.make_sources(L, n, W.sources_seed(3))
+    log("generated links and sources in %.1f s" % (time.time() - t0))
+    Ud, Nd, bd = dev(U), dev(N), dev(b)
+    links = H.Links(L, Ud, Nd)
+    torch.cuda.synchronize()
+    ws = H.empty_bytes(H.hisq_workspace_bytes(L, n, H.MODE_MIXED))
+    x = torch.empty_like(bd)
+    stream = torch.cuda.current_stream()
+
+    def step(profile=1):
+        p = H.hisq_default_params(mode=H.MODE_MIXED, naik=naik, tol=1e-10, profile=profile)
+        st, info = H.hisq_cg_solve(L, m, n, p, links.f64, links.packed(H.PREC_F32, naik), bd, x, ws)
+        return st, info
+
+    for w in range(args.warmup):
+        st, info = step()
+        log("warmup %d: status %d iters %s" % (w, st, list(info.iters[:n])))
+    torch.cuda.synchronize()
+    infos = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        st, info = step()
+        infos.append(info.to_dict(n))
+        log("step %d: status %d, %.3f s, iters %s, updates %d" % (
+            k, st, info.seconds, list(info.iters[:n]), info.reliable_updates))
+        if st != H.HISQ_OK:
+            raise SystemExit("solve failed: %s" % infos[-1])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # kernel-level figures from the HIP events recorded inside the timed steps
+    nk = "r14" if naik == H.NAIK_R14 else "full"
+    link_b = R.LINK_BYTES_F32[nk]
+    vec_b = R.VEC_BYTES_F32
+    bytes_oe = Vh * (link_b + 2 * vec_b * n)          # links, read p, write t
+    bytes_eo = Vh * (link_b + 6 * vec_b * n)          # links, read t, p, x, r; write x, r
+    bytes_pu = Vh * 3 * vec_b * n                     # read r, p; write p
+    tot_ms = [sum(i["kernel_ms"][c] for i in infos) for c in range(4)]
+    tot_n = [sum(i["kernel_launches"][c] for i in infos) for c in range(4)]
+    avg_ms = [tot_ms[c] / max(tot_n[c], 1) for c in range(4)]
+    gbps_oe = bytes_oe / (avg_ms[H.K_DSLASH_OE] * 1e-3) / 1e9
+    gbps_eo = bytes_eo / (avg_ms[H.K_DSLASH_EO] * 1e-3) / 1e9
+    gbps_pu = bytes_pu / (avg_ms[H.K_PUPDATE] * 1e-3) / 1e9
+    dslash_gbps = (bytes_oe + bytes_eo) / ((avg_ms[1] + avg_ms[2]) * 1e-3) / 1e9
+    dslash_gflops = 2 * Vh * R.FLOPS_PER_SITE_RHS * n / ((avg_ms[1] + avg_ms[2]) * 1e-3) / 1e9
+    if tot_ms[H.K_DSLASH_EO] >= tot_ms[H.K_DSLASH_OE]:
+        dom = ("dslash_eo_cg_epilogue", gbps_eo, bytes_eo, avg_ms[2])
+    else:
+        dom = ("dslash_oe_norm", gbps_oe, bytes_oe, avg_ms[1])
+    iters = infos[-1]["iters"]
+    result = {
+        "metric": METRIC,
+        "value": round(dslash_gbps, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded links eta*exp(i*%.1f*H), N=-(1/24)UUU, Gaussian sources)" % args.eps,
+        "config": {"workload": "HISQ even-odd CG, mixed FP32/FP64, %s Naik, %dx%dx%dx%d, %d rhs, m=%g"
+                               % (nk, L[0], L[1], L[2], L[3], n, m),
+                   "lattice": list(L), "nrhs": n, "mass": m, "tol": 1e-10, "naik": nk,
+                   "parallelism": "single GPU (rhs bundles shard with no communication)"},
+        "pct_hbm_peak": round(100 * dslash_gbps / HBM_PEAK_GBPS, 1),
+        "dslash_gflops": round(dslash_gflops, 1),
+        "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(dom[1], 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(dom[1] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": dom[2], "avg_launch_ms": round(dom[3], 5)},
+        "kernels": {"dslash_oe_norm": {"avg_ms": round(avg_ms[1], 5), "GBps": round(gbps_oe, 1),
+                                       "launches": tot_n[1]},
+                    "dslash_eo_cg_epilogue": {"avg_ms": round(avg_ms[2], 5), "GBps": round(gbps_eo, 1),
+                                              "launches": tot_n[2]},
+                    "pupdate": {"avg_ms": round(avg_ms[0], 5), "GBps": round(gbps_pu, 1),
+                                "launches": tot_n[0]},
+                    "reliable_update": {"avg_ms": round(avg_ms[3], 4), "count": tot_n[3]}},
+        "cg": {"mixed_seconds": round(ms_per_step / 1e3, 4), "iters": iters,
+               "reliable_updates": infos[-1]["reliable_updates"],
+               "rel_true_res_max": max(infos[-1]["rel_true_res"]),
+               "tile": {"rhs_per_thread": infos[-1]["rhs_per_thread"],
+                        "block": infos[-1]["block_size"]}},
+    }
+
+    if not args.no_fp64_compare:
+        # the plain FP64 1-rhs solver, 8 times in sequence, same sources and GPU
+        ws1 = H.empty_bytes(H.hisq_workspace_bytes(L, 1, H.MODE_FP64))
+        p = H.hisq_default_params(mode=H.MODE_FP64, tol=1e-10)
+        cols = [bd[:, :, k:k + 1].contiguous() for k in range(n)]
+        x1 = torch.empty_like(cols[0])
+        H.hisq_cg_solve(L, m, 1, p, links.f64, None, cols[0], x1, ws1)  # tune + warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it64 = []
+        for k in range(n):
+            st, info = H.hisq_cg_solve(L, m, 1, p, links.f64, None, cols[k], x1, ws1)
+            it64.append(info.iters[0])
+        torch.cuda.synchronize()
+        fp64_s = time.perf_counter() - t1
+        result["cg"]["fp64_1rhs_x%d_seconds" % n] = round(fp64_s, 4)
+        result["cg"]["fp64_iters"] = it64
+        result["cg"]["speedup_vs_fp64_1rhs"] = round(fp64_s / (ms_per_step / 1e3), 2)
+        log("FP64 %d x 1-rhs: %.3f s (iters %s)" % (n, fp64_s, it64))
+
+    if not args.no_sweep:
+        sweep = {}
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        for prec, nk2, tag in ((H.PREC_F64, H.NAIK_FULL, "f64"), (H.PREC_F32, H.NAIK_FULL, "f32"),
+                               (H.PREC_F32, H.NAIK_R14, "f32_r14")):
+            for nn in (1, 2, 4, 8):
+                dt = torch.complex128 if prec == H.PREC_F64 else torch.complex64
+                vin = bd[:, :, :nn].contiguous().to(dt)
+                vout = torch.empty_like(vin)
+                packed = links.packed(prec, nk2)
+                for _ in range(3):
+                    H.hisq_dslash(L, 1, nn, prec, nk2, packed, vin, vout)
+                reps = 20
+                ev0.record(stream)
+                for _ in range(reps):
+                    H.hisq_dslash(L, 1, nn, prec, nk2, packed, vin, vout)
+                ev1.record(stream)
+                ev1.synchronize()
+                ms = ev0.elapsed_time(ev1) / reps
+                scale = 2 if prec == H.PREC_F64 else 1
+                byt = Vh * scale * (R.LINK_BYTES_F32["r14" if nk2 == H.NAIK_R14 else "full"] + 2 * vec_b * nn)
+                sweep["%s_n%d" % (tag, nn)] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
+                                               "GFlops": round(Vh * R.FLOPS_PER_SITE_RHS * nn / ms / 1e6, 1)}
+        result["dslash_sweep"] = sweep
+        log("sweep", json.dumps(sweep))
+
+    if not args.no_cpu_baseline:
+        import oracle
+        vh = b[:, :, :n]
+        tc = time.perf_counter()
+        reps = 0
+        while True:
+            oracle.dslash_eo(L, U, N, vh, 1)
+            reps += 1
+            if time.perf_counter() - tc > args.cpu_seconds or reps >= 10:
+                break
+        cpu_s = (time.perf_counter() - tc) / reps
+        cpu_bytes = Vh * 2 * (R.LINK_BYTES_F32["full"] + 2 * vec_b * n)
+        result["cpu_baseline"] = {"value": round(cpu_bytes / cpu_s / 1e9, 3), "unit": "GB/s",
+                                  "cores": oracle.num_threads(), "kind": "oracle",
+                                  "sample": "%d FP64 half-Dslash applications, %s, %d rhs (%.1f s each)"
+                                            % (reps, "x".join(map(str, L)), n, cpu_s)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,6 +53,7 @@ def _load():
             Lp = ctypes.POINTER(ctypes.c_int)
             lib.orc_dslash_full.argtypes = [Lp, I, P, P, P, P]
             lib.orc_dslash_eo.argtypes = [Lp, I, I, P, P, P, P]
+            lib.orc_dslash_sites.argtypes = [Lp, I, I, P, P, P, ctypes.c_long, P, P]
             lib.orc_apply_A.argtypes = [Lp, I, D, P, P, P, P]
             lib.orc_cg.argtypes = [Lp, I, D, P, P, P, P, D, I, P, P, P, P]
             lib.orc_residual.argtypes = [Lp, I, D, P, P, P, P, P]
@@ -114,6 +115,17 @@ def dslash_eo(L, U, N, v, out_parity):
     _check(_load().orc_dslash_eo(_geom(L), v.shape[2], int(out_parity), _ptr(U), _ptr(N),
                                  _ptr(v), _ptr(w)))
     return w
+
+
+def dslash_sites(L, U, N, v, out_parity, sites):
+    """Half-lattice Dslash at chosen full-lattice sites of parity out_parity: (count, 3, n)."""
+    U, N = _links(L, U, N)
+    v = _c128(v)
+    sites = np.ascontiguousarray(sites, dtype=np.int64)
+    out = np.empty((sites.size, 3, v.shape[2]), dtype=np.complex128)
+    _check(_load().orc_dslash_sites(_geom(L), v.shape[2], int(out_parity), _ptr(U), _ptr(N),
+                                    _ptr(v), sites.size, _ptr(sites), _ptr(out)))
+    return out
 
 
 def apply_A(L, U, N, m, x):

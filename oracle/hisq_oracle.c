@@ -170,6 +170,29 @@ int orc_dslash_eo(const int* L, int n, int out_parity, const double* U, const do
     return 0;
 }
 
+/*
+ * The same half-lattice Dslash evaluated only at `count` chosen output sites
+ * (full-lattice indices, all of parity out_parity): out[j] = (D in)_{sites[j]},
+ * shape [count][3][n].  Used to check outputs of very large lattices site by site.
+ */
+int orc_dslash_sites(const int* L, int n, int out_parity, const double* U, const double* N,
+                     const double* in, long count, const long* sites, double* out)
+{
+    lat_t t;
+    int rc = lat_init(&t, L);
+    if (rc) return rc;
+    if (n < 1 || (out_parity != 0 && out_parity != 1) || !U || !N || !in || !out || count < 0 ||
+        (count > 0 && !sites))
+        return -1;
+    for (long j = 0; j < count; ++j)
+        if (sites[j] < 0 || sites[j] >= t.V || parity_of(&t, sites[j]) != out_parity) return -1;
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < count; ++j)
+        dslash_site(&t, n, (const zc*)U, (const zc*)N, (const zc*)in, halve, sites[j],
+                    (zc*)out + j * 3 * n);
+    return 0;
+}
+
 /* y = A x = 4 m^2 x - D_eo (D_oe x) on even half fields */
 static int apply_A_c(const lat_t* t, int n, double m, const zc* U, const zc* N,
                      const zc* x, zc* y)

@@ -1,0 +1,1163 @@
+// Host side of libhisq: argument checks, workspace layout, the autotuner, the
+// CG driver (polling, reliable updates, hipGraph capture) and the C ABI.
+//
+// The solver is the even-odd CG for A x = b with A = 4m^2 - D_eo D_oe and the
+// HISQ Dslash of Sec. 1 eq. (3), run on bundles of n rhs (eq. (4)); every rhs
+// has its own alpha, beta and convergence flag.  Per iteration three kernels
+// run: p = r + beta p (|p|^2), t = D_oe p (|t|^2, alpha), and
+// D_eo t fused with x += alpha p, r -= alpha (4m^2 p - D_eo t) (|r|^2, beta).
+// alpha uses <p, A p> = 4m^2 |p|^2 + |D_oe p|^2, which holds because D is
+// anti-Hermitian (D_eo^dag = -D_oe).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "hisq_internal.h"
+
+using namespace hisq;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(HISQ_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int check_geom(const hisq_geom* g, Lat* lat)
+{
+    if (!g) return fail(HISQ_EINVAL, "geometry is NULL");
+    long long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        if (g->L[mu] < 4 || (g->L[mu] % 2) != 0)
+            return fail(HISQ_EGEOM, "extent L[%d] = %d must be even and >= 4", mu, g->L[mu]);
+        V *= g->L[mu];
+    }
+    // 32-bit indexing of the packed link blocks: 144 complex per site and parity
+    if (V / 2 * 144 >= (1LL << 31)) return fail(HISQ_EGEOM, "lattice too large (V = %lld)", V);
+    *lat = make_lat(*g);
+    return HISQ_OK;
+}
+
+bool valid_nr(int n, int nr)
+{
+    if (nr < 1 || nr > n || n % nr != 0) return false;
+    const int G = n / nr;
+    return G == 1 || G == 2 || G == 4 || G == 8;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout (every region 256-byte aligned).
+struct Ws {
+    CgState* st = nullptr;
+    double* red = nullptr;
+    uint32_t* cnt = nullptr;
+    size_t cnt_bytes = 0;
+    d2* r64 = nullptr;  // FP64 residual (the iteration r in FP64 mode)
+    d2* t64 = nullptr;  // FP64 odd temporary (the iteration t in FP64 mode)
+    d2* p64 = nullptr;  // FP64 mode: search direction
+    f2* r32 = nullptr;  // MIXED: FP32 r, p, t, x_lo
+    f2* p32 = nullptr;
+    f2* t32 = nullptr;
+    f2* x32 = nullptr;
+    d2* y = nullptr;  // backward: adjoint solution, D_oe x, D_oe y
+    d2* tx = nullptr;
+    d2* sy = nullptr;
+};
+
+size_t ws_layout(const Lat& lat, int n, int mode, bool backward, char* base, Ws* w)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return base ? base + o : nullptr;
+    };
+    const size_t f64 = (size_t)lat.Vh * 3 * n * sizeof(d2);
+    const size_t f32 = (size_t)lat.Vh * 3 * n * sizeof(f2);
+    const size_t maxblocks = (size_t)lat.Vh * 8 / 64 + 1;  // block >= 64 threads, <= 8 per site
+    w->st = (CgState*)take(sizeof(CgState));
+    w->red = (double*)take(red_doubles(maxblocks) * sizeof(double));
+    w->cnt_bytes = align256(red_counters(maxblocks) * sizeof(uint32_t));
+    w->cnt = (uint32_t*)take(w->cnt_bytes);
+    w->r64 = (d2*)take(f64);
+    w->t64 = (d2*)take(f64);
+    if (mode == HISQ_MODE_FP64) {
+        w->p64 = (d2*)take(f64);
+    } else {
+        w->r32 = (f2*)take(f32);
+        w->p32 = (f2*)take(f32);
+        w->t32 = (f2*)take(f32);
+        w->x32 = (f2*)take(f32);
+    }
+    if (backward) {
+        w->y = (d2*)take(f64);
+        w->tx = (d2*)take(f64);
+        w->sy = (d2*)take(f64);
+    }
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// Packed link access.
+template <typename T>
+const cplx<T>* link_block(const void* packed, int Vh, bool r14, int parity)
+{
+    const char* b = reinterpret_cast<const char*>(packed) + kLinkHeaderBytes;
+    return reinterpret_cast<const cplx<T>*>(b) + (size_t)parity * link_block_elems(Vh, r14);
+}
+
+hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<double>& a,
+                     hipStream_t s)
+{
+    (void)r14;
+    return launch_dslash_f64(epi, n, t, a, s);
+}
+
+hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<float>& a,
+                     hipStream_t s)
+{
+    return r14 ? launch_dslash_f32r14(epi, n, t, a, s) : launch_dslash_f32(epi, n, t, a, s);
+}
+
+hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStream_t s)
+{
+    return launch_pupdate_f64(n, t, a, s);
+}
+
+hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<float>& a, hipStream_t s)
+{
+    return launch_pupdate_f32(n, t, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times the candidate tiles with the plain Dslash on the caller's
+// buffers and caches the fastest per (lattice, nrhs, precision, Naik storage).
+std::mutex g_tune_mu;
+std::map<std::string, Tile> g_tune_cache;
+int g_tune_mode = 0;
+int g_force_nr = 0, g_force_bs = 0;
+
+Tile default_tile(int n, int prec)
+{
+    Tile t{n, 128, 1};
+    if (prec == HISQ_PREC_F64 && n > 4) {
+        for (int nr = 4; nr >= 1; --nr)
+            if (valid_nr(n, nr)) {
+                t.nr = nr;
+                break;
+            }
+    }
+    return t;
+}
+
+std::string tune_key(const Lat& lat, int n, int prec, int naik, int epi)
+{
+    char buf[128];
+    snprintf(buf, sizeof(buf), "%dx%dx%dx%d/n%d/p%d/k%d/e%d", lat.L[0], lat.L[1], lat.L[2],
+             lat.L[3], n, prec, naik, epi);
+    return buf;
+}
+
+// epi: EPI_PLAIN times the bare Dslash (hisq_dslash); EPI_NORM times the
+// solver's reducing kernel, whose per-work-group reduction cost depends on the
+// tile (probe.state/red/cnt must then be valid, counters zero, rhs active).
+template <typename T>
+int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& probe, hipStream_t s,
+             Tile* out, int epi = EPI_PLAIN)
+{
+    int mode, fnr, fbs;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        mode = g_tune_mode;
+        fnr = g_force_nr;
+        fbs = g_force_bs;
+    }
+    if (mode == 1 && valid_nr(n, fnr)) {
+        *out = Tile{fnr, fbs, 1};
+        return HISQ_OK;
+    }
+    if (mode != 0) {
+        *out = default_tile(n, prec);
+        return HISQ_OK;
+    }
+    const std::string key = tune_key(lat, n, prec, r14 ? 1 : 0, epi);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return HISQ_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    Tile best = default_tile(n, prec);
+    float best_ms = 1e30f;
+    const int bss[3] = {64, 128, 256};
+    for (int G = 1; G <= 8; G *= 2) {
+        if (n % G != 0) continue;
+        const int nr = n / G;
+        for (int bi = 0; bi < 3; ++bi)
+            for (int remap = 0; remap < 2; ++remap) {
+                const Tile c{nr, bss[bi], remap};
+                if (launch_ds(epi, n, r14, c, probe, s) != hipSuccess) continue;
+                HIP_TRY(hipEventRecord(e0, s));
+                for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, r14, c, probe, s));
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    *out = best;
+    return HISQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-thread resources: pinned host copy of the CG state and a capture stream.
+struct ThreadRes {
+    CgState* host_state = nullptr;
+    std::map<int, hipStream_t> capture;
+    ~ThreadRes()
+    {
+        // Process teardown: the runtime may already be gone; release nothing.
+    }
+};
+thread_local ThreadRes g_res;
+
+int host_state(CgState** out)
+{
+    if (!g_res.host_state) {
+        void* p = nullptr;
+        HIP_TRY(hipHostMalloc(&p, sizeof(CgState) * HISQ_MAX_PROBLEMS, hipHostMallocDefault));
+        g_res.host_state = (CgState*)p;
+    }
+    *out = g_res.host_state;
+    return HISQ_OK;
+}
+
+int capture_stream(hipStream_t* out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto it = g_res.capture.find(dev);
+    if (it == g_res.capture.end()) {
+        hipStream_t s;
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        it = g_res.capture.emplace(dev, s).first;
+    }
+    *out = it->second;
+    return HISQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The CG driver.  A solve is a set of problems (one bundle each); with a single
+// problem the iteration kernels are specialised for its bundle and tile, with
+// several every CG phase is one batched launch over all of them.
+struct Prob {
+    Lat lat{};
+    int n = 0;
+    double mass = 0, m4 = 0;
+    const void* links64 = nullptr;
+    const void* links32 = nullptr;
+    const d2* b = nullptr;
+    d2* x = nullptr;
+    Ws w;
+    Tile t64{}, t32{};
+    CgState* hs = nullptr;  // pinned host copy
+    double bb[kMaxRhs] = {}, maxrr[kMaxRhs] = {};
+    bool fin[kMaxRhs] = {};
+    int restarts[kMaxRhs] = {};
+    double rr_iter[kMaxRhs] = {};
+    int st_final[kMaxRhs] = {};
+    size_t ncplx() const { return (size_t)lat.Vh * 3 * n; }
+};
+
+struct Engine {
+    std::vector<Prob> P;
+    hisq_params prm{};
+    bool mixed = false, r14 = false;
+    hipStream_t s = nullptr;
+    CgState* states = nullptr;  // device, contiguous, one per problem
+    void* table = nullptr;      // device BatchTable (several problems)
+    int batch_bs = 128, batch_blocks = 0;
+    std::vector<hipEvent_t> ev;
+    double kms[HISQ_K_COUNT] = {0, 0, 0, 0};
+    int klaunch[HISQ_K_COUNT] = {0, 0, 0, 0};
+    int updates = 0, polls = 0;
+
+    DslashArgs<double> args64(const Prob& q, int parity) const
+    {
+        DslashArgs<double> a{};
+        a.lat = q.lat;
+        a.parity = parity;
+        a.links = link_block<double>(q.links64, q.lat.Vh, false, parity);
+        a.mass4 = q.m4;
+        a.state = q.w.st;
+        a.red = q.w.red;
+        a.cnt = q.w.cnt;
+        return a;
+    }
+
+    // r64 = b - A x for the selected rhs of q (FP64 links); |r|^2 -> rr_true.
+    int true_residual(const Prob& q)
+    {
+        DslashArgs<double> a = args64(q, 1);
+        a.in = q.x;
+        a.out = q.w.t64;
+        HIP_TRY(launch_ds(EPI_PLAIN, q.n, false, q.t64, a, s));
+        DslashArgs<double> c = args64(q, 0);
+        c.in = q.w.t64;
+        c.out = q.w.r64;
+        c.b = q.b;
+        c.xh = q.x;
+        HIP_TRY(launch_ds(EPI_RESID, q.n, false, q.t64, c, s));
+        return HISQ_OK;
+    }
+
+    template <typename T>
+    void iter_args(const Prob& q, PupdateArgs<T>& k1, DslashArgs<T>& k2, DslashArgs<T>& k3) const
+    {
+        const void* L = std::is_same<T, float>::value ? q.links32 : q.links64;
+        const bool rr = r14 && std::is_same<T, float>::value;
+        cplx<T>* r;
+        cplx<T>* p;
+        cplx<T>* t;
+        cplx<T>* x;
+        if constexpr (std::is_same<T, float>::value) {
+            r = q.w.r32;
+            p = q.w.p32;
+            t = q.w.t32;
+            x = q.w.x32;
+        } else {
+            r = q.w.r64;
+            p = q.w.p64;
+            t = q.w.t64;
+            x = q.x;
+        }
+        const Tile& tile = std::is_same<T, float>::value ? q.t32 : q.t64;
+        k1 = PupdateArgs<T>{};
+        k1.lat = q.lat;
+        k1.r = r;
+        k1.p = p;
+        k1.state = q.w.st;
+        k1.red = q.w.red;
+        k1.cnt = q.w.cnt;
+        k1.remap = tile.remap;
+        k2 = DslashArgs<T>{};
+        k2.lat = q.lat;
+        k2.parity = 1;
+        k2.links = link_block<T>(L, q.lat.Vh, rr, 1);
+        k2.in = p;
+        k2.out = t;
+        k2.mass4 = q.m4;
+        k2.state = q.w.st;
+        k2.red = q.w.red;
+        k2.cnt = q.w.cnt;
+        k2.remap = tile.remap;
+        k3 = k2;
+        k3.parity = 0;
+        k3.links = link_block<T>(L, q.lat.Vh, rr, 0);
+        k3.in = t;
+        k3.out = nullptr;
+        k3.p = p;
+        k3.x = x;
+        k3.r = r;
+    }
+
+    template <typename T>
+    int emit_single(hipStream_t st, hipEvent_t* evs)
+    {
+        const Prob& q = P[0];
+        PupdateArgs<T> k1;
+        DslashArgs<T> k2, k3;
+        iter_args<T>(q, k1, k2, k3);
+        const Tile& tile = std::is_same<T, float>::value ? q.t32 : q.t64;
+        const bool rr = r14 && std::is_same<T, float>::value;
+        if (evs) HIP_TRY(hipEventRecord(evs[0], st));
+        HIP_TRY(launch_pup(q.n, tile, k1, st));
+        if (evs) HIP_TRY(hipEventRecord(evs[1], st));
+        HIP_TRY(launch_ds(EPI_NORM, q.n, rr, tile, k2, st));
+        if (evs) HIP_TRY(hipEventRecord(evs[2], st));
+        HIP_TRY(launch_ds(EPI_CG, q.n, rr, tile, k3, st));
+        if (evs) HIP_TRY(hipEventRecord(evs[3], st));
+        return HISQ_OK;
+    }
+
+    template <typename T>
+    int emit_batched(hipStream_t st, hipEvent_t* evs)
+    {
+        const BatchTable<T>* tab = reinterpret_cast<const BatchTable<T>*>(table);
+        if (evs) HIP_TRY(hipEventRecord(evs[0], st));
+        if constexpr (std::is_same<T, float>::value) {
+            HIP_TRY(launch_pupdate_batched_f32(tab, batch_blocks, batch_bs, st));
+            if (evs) HIP_TRY(hipEventRecord(evs[1], st));
+            HIP_TRY(launch_dslash_batched_f32(EPI_NORM, r14, tab, batch_blocks, batch_bs, st));
+            if (evs) HIP_TRY(hipEventRecord(evs[2], st));
+            HIP_TRY(launch_dslash_batched_f32(EPI_CG, r14, tab, batch_blocks, batch_bs, st));
+        } else {
+            HIP_TRY(launch_pupdate_batched_f64(tab, batch_blocks, batch_bs, st));
+            if (evs) HIP_TRY(hipEventRecord(evs[1], st));
+            HIP_TRY(launch_dslash_batched_f64(EPI_NORM, tab, batch_blocks, batch_bs, st));
+            if (evs) HIP_TRY(hipEventRecord(evs[2], st));
+            HIP_TRY(launch_dslash_batched_f64(EPI_CG, tab, batch_blocks, batch_bs, st));
+        }
+        if (evs) HIP_TRY(hipEventRecord(evs[3], st));
+        return HISQ_OK;
+    }
+
+    int emit_block(hipStream_t st, int iters, bool with_events)
+    {
+        for (int j = 0; j < iters; ++j) {
+            hipEvent_t* evs = with_events ? &ev[4 * j] : nullptr;
+            int rc;
+            if (P.size() == 1)
+                rc = mixed ? emit_single<float>(st, evs) : emit_single<double>(st, evs);
+            else
+                rc = mixed ? emit_batched<float>(st, evs) : emit_batched<double>(st, evs);
+            if (rc) return rc;
+        }
+        return HISQ_OK;
+    }
+
+    template <typename T>
+    int upload_table(void* host_buf)
+    {
+        BatchTable<T>* tab = reinterpret_cast<BatchTable<T>*>(host_buf);
+        std::memset(tab, 0, sizeof(*tab));
+        int start = 0;
+        for (size_t j = 0; j < P.size(); ++j) {
+            const Prob& q = P[j];
+            BatchProb<T>& bp = tab->p[j];
+            iter_args<T>(q, bp.k1, bp.k2, bp.k3);
+            const Tile& tile = std::is_same<T, float>::value ? q.t32 : q.t64;
+            bp.n = q.n;
+            bp.nr = batched_nr_ok(q.n, tile.nr) ? tile.nr : q.n;
+            bp.k1.remap = bp.k2.remap = bp.k3.remap = 0;
+            const long threads = (long)q.lat.Vh * (q.n / bp.nr);
+            bp.nblocks = (int)((threads + batch_bs - 1) / batch_bs);
+            bp.k1.ntiles = bp.k2.ntiles = bp.k3.ntiles = bp.nblocks;
+            bp.block_start = start;
+            start += bp.nblocks;
+        }
+        tab->nprob = (int)P.size();
+        tab->total_blocks = start;
+        batch_blocks = start;
+        HIP_TRY(hipMemcpyAsync(table, tab, sizeof(BatchTable<T>), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return HISQ_OK;
+    }
+
+    int read_states(CgState* host)
+    {
+        HIP_TRY(hipMemcpyAsync(host, states, sizeof(CgState) * P.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return HISQ_OK;
+    }
+
+    int write_states(CgState* host)
+    {
+        HIP_TRY(hipMemcpyAsync(states, host, sizeof(CgState) * P.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return HISQ_OK;
+    }
+
+    int poll_block_size() const
+    {
+        if (prm.poll_every > 0) return prm.poll_every;
+        double bytes = 0;
+        for (const Prob& q : P)
+            bytes += (double)q.lat.Vh * (mixed ? (2304.0 + 264.0 * q.n) : (4608.0 + 528.0 * q.n));
+        const double est = bytes / 4.0e12 + 3 * 4.0e-6;
+        const int k = (int)std::ceil(2.0e-3 / est);
+        return std::max(4, std::min(64, k));
+    }
+
+    int collect_events(int iters)
+    {
+        for (int j = 0; j < iters; ++j)
+            for (int c = 0; c < 3; ++c) {
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[4 * j + c], ev[4 * j + c + 1]));
+                kms[c] += ms;
+                klaunch[c] += 1;
+            }
+        return HISQ_OK;
+    }
+
+    int setup(CgState* host);
+    int poll_and_update(CgState* host);
+    int finish(CgState* host, hisq_info* infos, double seconds);
+    int run(hisq_info* infos);
+};
+
+int Engine::setup(CgState* host)
+{
+    int rc;
+    for (Prob& q : P) {
+        const size_t nc = q.ncplx();
+        HIP_TRY(launch_zero(q.w.cnt, q.w.cnt_bytes, s));
+        HIP_TRY(launch_state_reset(q.w.st, q.n, 0, s));
+        if (!prm.use_x0) HIP_TRY(launch_zero(q.x, nc * sizeof(d2), s));
+        HIP_TRY(launch_norm2_f64(q.b, q.lat.Vh, q.n, q.w.st->aux, q.w.red, q.w.cnt, s));
+        if ((rc = true_residual(q))) return rc;
+        if (mixed) {
+            HIP_TRY(launch_to_f32_sel(q.w.r64, q.w.r32, nc, q.n, q.w.st, s));
+            HIP_TRY(launch_zero(q.w.x32, nc * sizeof(f2), s));
+            HIP_TRY(launch_zero(q.w.p32, nc * sizeof(f2), s));
+        } else {
+            HIP_TRY(launch_zero(q.w.p64, nc * sizeof(d2), s));
+        }
+    }
+    if ((rc = read_states(host))) return rc;
+    const double tol2 = prm.tol * prm.tol;
+    bool any_zero_b = false;
+    for (size_t j = 0; j < P.size(); ++j) {
+        Prob& q = P[j];
+        CgState* h = &host[j];
+        q.hs = h;
+        for (int k = 0; k < q.n; ++k) {
+            q.bb[k] = h->aux[k];
+            h->thresh[k] = tol2 * q.bb[k];
+            h->rr[k] = h->rr_true[k];
+            q.maxrr[k] = h->rr[k];
+            h->beta[k] = 0.0;
+            h->iters[k] = 0;
+            h->status[k] = HISQ_OK;
+            q.restarts[k] = 0;
+            q.fin[k] = !(h->rr[k] > h->thresh[k]) || prm.maxiter == 0;
+            h->active[k] = q.fin[k] ? 0 : 1;
+            h->sel[k] = q.bb[k] == 0.0 ? 1 : 0;
+            any_zero_b = any_zero_b || q.bb[k] == 0.0;
+        }
+        h->maxiter = prm.maxiter;
+    }
+    if ((rc = write_states(host))) return rc;
+    if (any_zero_b) {
+        // b_k = 0: the solution is exactly 0, whatever the start vector
+        for (Prob& q : P) HIP_TRY(launch_zero_sel(q.x, q.ncplx(), q.n, q.w.st, s));
+        for (size_t j = 0; j < P.size(); ++j)
+            for (int k = 0; k < P[j].n; ++k) host[j].sel[k] = 0;
+        if ((rc = write_states(host))) return rc;
+    }
+    return HISQ_OK;
+}
+
+// After a poll: choose the rhs that need a true-residual pass, run it, and
+// decide convergence, restarts and reliable updates.
+int Engine::poll_and_update(CgState* host)
+{
+    int rc;
+    bool any = false;
+    for (Prob& q : P) {
+        CgState* h = q.hs;
+        bool any_q = false;
+        for (int k = 0; k < q.n; ++k) {
+            h->sel[k] = 0;
+            if (q.fin[k]) continue;
+            if (h->status[k] == HISQ_BREAKDOWN) {
+                if (mixed && q.restarts[k] < 3) {
+                    h->sel[k] = 1;  // recover: reliable update, restart with p = r
+                } else {
+                    q.fin[k] = true;
+                    continue;
+                }
+            } else if (!h->active[k]) {
+                h->sel[k] = 1;  // iterated residual passed (or maxiter): check the true one
+            } else if (mixed && h->rr[k] < prm.delta * prm.delta * q.maxrr[k]) {
+                h->sel[k] = 1;  // reliable update
+            }
+            any_q = any_q || h->sel[k];
+        }
+        if (any_q && mixed) {
+            // one FP64 pass serves the whole bundle: update every running rhs
+            for (int k = 0; k < q.n; ++k)
+                if (!q.fin[k]) h->sel[k] = 1;
+        }
+        any = any || any_q;
+    }
+    if (!any) return HISQ_OK;
+    if ((rc = write_states(host))) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prm.profile) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    for (Prob& q : P) {
+        bool any_q = false;
+        for (int k = 0; k < q.n; ++k) any_q = any_q || q.hs->sel[k];
+        if (!any_q) continue;
+        if (mixed) HIP_TRY(launch_accum_sel(q.x, q.w.x32, q.ncplx(), q.n, q.w.st, s));
+        if ((rc = true_residual(q))) return rc;
+        if (mixed) HIP_TRY(launch_to_f32_sel(q.w.r64, q.w.r32, q.ncplx(), q.n, q.w.st, s));
+    }
+    if (prm.profile) HIP_TRY(hipEventRecord(e1, s));
+    ++updates;
+    if ((rc = read_states(host))) return rc;
+    if (prm.profile) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        kms[HISQ_K_RELIABLE] += ms;
+        klaunch[HISQ_K_RELIABLE] += 1;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+    }
+    for (Prob& q : P) {
+        CgState* h = q.hs;
+        for (int k = 0; k < q.n; ++k) {
+            if (!h->sel[k]) continue;
+            const double rt = h->rr_true[k];
+            if (rt <= h->thresh[k] && h->status[k] != HISQ_BREAKDOWN) {
+                q.fin[k] = true;
+                h->active[k] = 0;
+                h->status[k] = HISQ_OK;
+                continue;
+            }
+            if (h->iters[k] >= prm.maxiter) {
+                q.fin[k] = true;
+                h->active[k] = 0;
+                h->status[k] = HISQ_NOT_CONVERGED;
+                continue;
+            }
+            if (h->status[k] == HISQ_BREAKDOWN) {
+                q.restarts[k] += 1;
+                h->status[k] = HISQ_OK;
+                h->beta[k] = 0.0;  // restart: p = r
+            } else if (!mixed || !h->active[k]) {
+                h->beta[k] = 0.0;  // restart from the true residual
+            }
+            h->rr[k] = rt;
+            q.maxrr[k] = rt;
+            h->active[k] = 1;
+        }
+        for (int k = 0; k < q.n; ++k) h->sel[k] = 0;
+    }
+    return write_states(host);
+}
+
+int Engine::finish(CgState* host, hisq_info* infos, double seconds)
+{
+    int rc;
+    for (size_t j = 0; j < P.size(); ++j) {
+        Prob& q = P[j];
+        for (int k = 0; k < q.n; ++k) {
+            q.st_final[k] = host[j].status[k];
+            q.rr_iter[k] = host[j].rr[k];
+            host[j].sel[k] = 1;
+        }
+    }
+    if ((rc = write_states(host))) return rc;
+    for (Prob& q : P) {
+        if (mixed) HIP_TRY(launch_accum_sel(q.x, q.w.x32, q.ncplx(), q.n, q.w.st, s));
+        if ((rc = true_residual(q))) return rc;
+    }
+    if ((rc = read_states(host))) return rc;
+    int worst = HISQ_OK;
+    for (size_t j = 0; j < P.size(); ++j) {
+        Prob& q = P[j];
+        hisq_info* info = infos ? &infos[j] : nullptr;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            const Tile& t = mixed ? q.t32 : q.t64;
+            info->block_size = P.size() == 1 ? t.bs : batch_bs;
+            info->rhs_per_thread = t.nr;
+        }
+        int maxit = 0;
+        for (int k = 0; k < q.n; ++k) {
+            int stk = q.st_final[k];
+            // |b| = 0 gives x = 0 exactly; a non-finite |b| can never converge
+            const double rel = q.bb[k] > 0 ? std::sqrt(host[j].rr_true[k] / q.bb[k])
+                                           : (q.bb[k] == 0.0 ? 0.0 : NAN);
+            if (stk == HISQ_OK && !(rel <= prm.tol)) stk = HISQ_NOT_CONVERGED;
+            worst = std::max(worst, stk);
+            maxit = std::max(maxit, host[j].iters[k]);
+            if (info) {
+                info->iters[k] = host[j].iters[k];
+                info->status[k] = stk;
+                info->rel_true_res[k] = rel;
+                info->rel_iter_res[k] =
+                    q.bb[k] > 0 ? std::sqrt(std::max(0.0, q.rr_iter[k]) / q.bb[k]) : 0.0;
+            }
+        }
+        if (info) {
+            info->reliable_updates = updates;
+            info->polls = polls;
+            info->total_iters = maxit;
+            info->seconds = seconds;
+            for (int c = 0; c < HISQ_K_COUNT; ++c) {
+                info->kernel_ms[c] = kms[c];
+                info->kernel_launches[c] = klaunch[c];
+            }
+        }
+    }
+    return worst;
+}
+
+int Engine::run(hisq_info* infos)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    int rc;
+    CgState* host = nullptr;
+    if ((rc = host_state(&host))) return rc;
+
+    // tiles (autotuned per problem on the reducing D_oe kernel; the state and
+    // counters are armed for it here and reset again by setup())
+    for (Prob& q : P) {
+        HIP_TRY(launch_zero(q.w.cnt, q.w.cnt_bytes, s));
+        HIP_TRY(launch_state_reset(q.w.st, q.n, 1, s));
+        DslashArgs<double> probe = args64(q, 1);
+        probe.in = q.x;
+        probe.out = q.w.t64;
+        if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F64, false, probe, s, &q.t64, EPI_NORM))) return rc;
+        if (mixed) {
+            DslashArgs<float> p32{};
+            p32.lat = q.lat;
+            p32.parity = 1;
+            p32.links = link_block<float>(q.links32, q.lat.Vh, r14, 1);
+            p32.in = q.w.p32;
+            p32.out = q.w.t32;
+            p32.mass4 = q.m4;
+            p32.state = q.w.st;
+            p32.red = q.w.red;
+            p32.cnt = q.w.cnt;
+            if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F32, r14, p32, s, &q.t32, EPI_NORM))) return rc;
+        }
+    }
+    if ((rc = setup(host))) return rc;
+    if (P.size() > 1) {
+        // one work-group size for the batched launch: the largest problem's
+        size_t big = 0;
+        for (size_t j = 1; j < P.size(); ++j)
+            if (P[j].lat.Vh * P[j].n > P[big].lat.Vh * P[big].n) big = j;
+        batch_bs = mixed ? P[big].t32.bs : P[big].t64.bs;
+        static thread_local std::vector<char> tabbuf;
+        tabbuf.resize(std::max(sizeof(BatchTable<double>), sizeof(BatchTable<float>)));
+        rc = mixed ? upload_table<float>(tabbuf.data()) : upload_table<double>(tabbuf.data());
+        if (rc) return rc;
+    }
+
+    const int kblk = poll_block_size();
+    const bool profile = prm.profile != 0;
+    if (profile) {
+        ev.resize(4 * kblk);
+        for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // Event timestamps are not available for events recorded inside a graph, so
+    // a profiled solve launches its kernels directly on the stream.
+    if (prm.use_graph && !profile) {
+        hipStream_t cap;
+        if ((rc = capture_stream(&cap))) return rc;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+        rc = emit_block(cap, kblk, profile);
+        const hipError_t ce = hipStreamEndCapture(cap, &graph);
+        if (rc) return rc;
+        HIP_TRY(ce);
+        HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    auto running = [&]() {
+        for (const Prob& q : P)
+            for (int k = 0; k < q.n; ++k)
+                if (!q.fin[k]) return true;
+        return false;
+    };
+    while (running()) {
+        if (exec) {
+            HIP_TRY(hipGraphLaunch(exec, s));
+        } else if ((rc = emit_block(s, kblk, profile))) {
+            return rc;
+        }
+        if ((rc = read_states(host))) return rc;
+        ++polls;
+        if (profile && (rc = collect_events(kblk))) return rc;
+        if ((rc = poll_and_update(host))) return rc;
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    for (auto& e : ev) hipEventDestroy(e);
+    ev.clear();
+    const double secs =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    return finish(host, infos, secs);
+}
+
+int check_params(const hisq_params* p, int n)
+{
+    if (!p) return fail(HISQ_EINVAL, "params is NULL");
+    if (n < 1 || n > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", n);
+    if (p->mode != HISQ_MODE_FP64 && p->mode != HISQ_MODE_MIXED)
+        return fail(HISQ_EINVAL, "unknown mode %d", p->mode);
+    if (p->naik != HISQ_NAIK_FULL && p->naik != HISQ_NAIK_R14)
+        return fail(HISQ_EINVAL, "unknown naik storage %d", p->naik);
+    if (!(p->tol > 0) || !std::isfinite(p->tol)) return fail(HISQ_EINVAL, "tol must be > 0");
+    if (p->maxiter < 0) return fail(HISQ_EINVAL, "maxiter must be >= 0");
+    if (p->mode == HISQ_MODE_MIXED && !(p->delta > 0 && p->delta < 1))
+        return fail(HISQ_EINVAL, "delta must be in (0, 1)");
+    if (p->poll_every < 0) return fail(HISQ_EINVAL, "poll_every must be >= 0");
+    return HISQ_OK;
+}
+
+int solve_impl(double mass, int nrhs, const hisq_params* p, const void* links64,
+               const void* links32, const double* b_e, double* x_e, const Ws& w, hisq_info* info,
+               void* stream, const Lat& lat)
+{
+    Engine E;
+    E.prm = *p;
+    E.mixed = p->mode == HISQ_MODE_MIXED;
+    E.r14 = E.mixed && p->naik == HISQ_NAIK_R14;
+    E.s = reinterpret_cast<hipStream_t>(stream);
+    Prob q;
+    q.lat = lat;
+    q.n = nrhs;
+    q.mass = mass;
+    q.m4 = 4.0 * mass * mass;
+    q.links64 = links64;
+    q.links32 = links32;
+    q.b = reinterpret_cast<const d2*>(b_e);
+    q.x = reinterpret_cast<d2*>(x_e);
+    q.w = w;
+    E.states = w.st;
+    E.P.push_back(q);
+    return E.run(info);
+}
+
+// Batched workspace: the states of all problems side by side, the batch
+// table, then each problem's own regions.
+size_t batched_layout(int nprob, const hisq_problem* probs, int mode, char* base,
+                      std::vector<Ws>* ws, CgState** states, void** table)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return base ? base + o : nullptr;
+    };
+    *states = (CgState*)take(sizeof(CgState) * nprob);
+    *table = take(std::max(sizeof(BatchTable<double>), sizeof(BatchTable<float>)));
+    ws->assign(nprob, Ws());
+    for (int j = 0; j < nprob; ++j) {
+        const Lat lat = make_lat(probs[j].geom);
+        Ws w;
+        const size_t need = ws_layout(lat, probs[j].nrhs, mode, false, nullptr, &w);
+        char* region = take(need);
+        ws_layout(lat, probs[j].nrhs, mode, false, region, &w);
+        w.st = base ? *states + j : nullptr;
+        (*ws)[j] = w;
+    }
+    return off;
+}
+
+int check_problems(int nprob, const hisq_problem* probs, int mode)
+{
+    if (nprob < 1 || nprob > HISQ_MAX_PROBLEMS)
+        return fail(HISQ_EINVAL, "nprob = %d outside 1..%d", nprob, HISQ_MAX_PROBLEMS);
+    if (!probs) return fail(HISQ_EINVAL, "problems is NULL");
+    for (int j = 0; j < nprob; ++j) {
+        Lat lat;
+        int rc = check_geom(&probs[j].geom, &lat);
+        if (rc) return rc;
+        if (probs[j].nrhs < 1 || probs[j].nrhs > HISQ_MAX_RHS)
+            return fail(HISQ_EINVAL, "problem %d: nrhs = %d outside 1..8", j, probs[j].nrhs);
+        if (!probs[j].links64 || !probs[j].b || !probs[j].x)
+            return fail(HISQ_EINVAL, "problem %d: NULL pointer", j);
+        if (mode == HISQ_MODE_MIXED && !probs[j].links32)
+            return fail(HISQ_EINVAL, "problem %d: MIXED mode needs FP32 links", j);
+        if (!std::isfinite(probs[j].mass)) return fail(HISQ_EINVAL, "problem %d: bad mass", j);
+    }
+    return HISQ_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+void hisq_default_params(hisq_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->mode = HISQ_MODE_FP64;
+    p->naik = HISQ_NAIK_FULL;
+    p->tol = 1e-10;
+    p->maxiter = 20000;
+    p->delta = 0.1;
+    p->poll_every = 0;
+    p->use_x0 = 0;
+    p->use_graph = 1;
+    p->profile = 0;
+}
+
+size_t hisq_links_bytes(const hisq_geom* g, int prec, int naik)
+{
+    Lat lat;
+    if (check_geom(g, &lat)) return 0;
+    if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return 0;
+    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return 0;
+    if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32) return 0;
+    const size_t elem = prec == HISQ_PREC_F64 ? sizeof(d2) : sizeof(f2);
+    return kLinkHeaderBytes + 2 * link_block_elems(lat.Vh, naik == HISQ_NAIK_R14) * elem;
+}
+
+size_t hisq_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
+{
+    Lat lat;
+    if (check_geom(g, &lat)) return 0;
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return 0;
+    if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
+    Ws w;
+    return ws_layout(lat, nrhs, mode, false, nullptr, &w);
+}
+
+size_t hisq_backward_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
+{
+    Lat lat;
+    if (check_geom(g, &lat)) return 0;
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return 0;
+    if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
+    Ws w;
+    return ws_layout(lat, nrhs, mode, true, nullptr, &w);
+}
+
+int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int prec, int naik,
+                    void* packed, void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_geom(g, &lat);
+    if (rc) return rc;
+    if (!U || !N || !packed) return fail(HISQ_EINVAL, "NULL pointer");
+    if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
+    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return fail(HISQ_EINVAL, "bad naik %d", naik);
+    if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32)
+        return fail(HISQ_EINVAL, "r14 Naik storage is FP32 only");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_pack(lat, reinterpret_cast<const d2*>(U), reinterpret_cast<const d2*>(N), prec,
+                        naik, packed, s));
+    if (naik == HISQ_NAIK_R14) {
+        uint32_t bits = 0;
+        const LinkHeader* h = reinterpret_cast<const LinkHeader*>(packed);
+        HIP_TRY(hipMemcpyAsync(&bits, &h->r14_err_bits, sizeof(bits), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float err;
+        std::memcpy(&err, &bits, sizeof(err));
+        if (!(err <= kR14Tolerance))
+            return fail(HISQ_EPACK, "r14 round-trip error %g: Naik links are not s * U(3)", err);
+    }
+    return HISQ_OK;
+}
+
+int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik,
+                const void* packed, const void* in, void* out, void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_geom(g, &lat);
+    if (rc) return rc;
+    if (!packed || !in || !out) return fail(HISQ_EINVAL, "NULL pointer");
+    if (out_parity != 0 && out_parity != 1) return fail(HISQ_EINVAL, "out_parity must be 0 or 1");
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", nrhs);
+    if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
+    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return fail(HISQ_EINVAL, "bad naik %d", naik);
+    if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32)
+        return fail(HISQ_EINVAL, "r14 Naik storage is FP32 only");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool r14 = naik == HISQ_NAIK_R14;
+    Tile t;
+    if (prec == HISQ_PREC_F64) {
+        DslashArgs<double> a{};
+        a.lat = lat;
+        a.parity = out_parity;
+        a.links = link_block<double>(packed, lat.Vh, false, out_parity);
+        a.in = reinterpret_cast<const d2*>(in);
+        a.out = reinterpret_cast<d2*>(out);
+        if ((rc = get_tile(lat, nrhs, prec, false, a, s, &t))) return rc;
+        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s));
+    } else {
+        DslashArgs<float> a{};
+        a.lat = lat;
+        a.parity = out_parity;
+        a.links = link_block<float>(packed, lat.Vh, r14, out_parity);
+        a.in = reinterpret_cast<const f2*>(in);
+        a.out = reinterpret_cast<f2*>(out);
+        if ((rc = get_tile(lat, nrhs, prec, r14, a, s, &t))) return rc;
+        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, r14, t, a, s));
+    }
+    return HISQ_OK;
+}
+
+int hisq_cg_solve(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                  const void* links64, const void* links32, const double* b_e, double* x_e,
+                  void* ws, size_t ws_bytes, hisq_info* info, void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_geom(g, &lat);
+    if (rc) return rc;
+    if ((rc = check_params(p, nrhs))) return rc;
+    if (!links64 || !b_e || !x_e || !ws) return fail(HISQ_EINVAL, "NULL pointer");
+    if (p->mode == HISQ_MODE_MIXED && !links32)
+        return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
+    if (!std::isfinite(mass)) return fail(HISQ_EINVAL, "mass must be finite");
+    Ws w;
+    const size_t need = ws_layout(lat, nrhs, p->mode, false, nullptr, &w);
+    if (ws_bytes < need)
+        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    ws_layout(lat, nrhs, p->mode, false, reinterpret_cast<char*>(ws), &w);
+    return solve_impl(mass, nrhs, p, links64, links32, b_e, x_e, w, info, stream, lat);
+}
+
+int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                           const void* links64, const void* links32, const double* x_e,
+                           const double* grad_x, double* grad_U, double* grad_N, double* grad_m,
+                           double* grad_b, void* ws, size_t ws_bytes, hisq_info* info,
+                           void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_geom(g, &lat);
+    if (rc) return rc;
+    if ((rc = check_params(p, nrhs))) return rc;
+    if (!links64 || !x_e || !grad_x || !grad_U || !grad_N || !grad_m || !ws)
+        return fail(HISQ_EINVAL, "NULL pointer");
+    if (p->mode == HISQ_MODE_MIXED && !links32)
+        return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
+    Ws w;
+    const size_t need = ws_layout(lat, nrhs, p->mode, true, nullptr, &w);
+    if (ws_bytes < need)
+        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    ws_layout(lat, nrhs, p->mode, true, reinterpret_cast<char*>(ws), &w);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    d2* y = grad_b ? reinterpret_cast<d2*>(grad_b) : w.y;
+    // adjoint solve: A is Hermitian, so A y = grad_x uses the same operator
+    hisq_params q = *p;
+    q.use_x0 = 0;
+    const int st = solve_impl(mass, nrhs, &q, links64, links32, grad_x, (double*)y, w, info,
+                              stream, lat);
+    if (st < 0) return st;
+    // t = D_oe x, s = D_oe y (FP64), then one thread per link
+    Tile t = default_tile(nrhs, HISQ_PREC_F64);
+    DslashArgs<double> a{};
+    a.lat = lat;
+    a.parity = 1;
+    a.links = link_block<double>(links64, lat.Vh, false, 1);
+    a.in = reinterpret_cast<const d2*>(x_e);
+    a.out = w.tx;
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s));
+    a.in = y;
+    a.out = w.sy;
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s));
+    HIP_TRY(launch_force(lat, nrhs, reinterpret_cast<const d2*>(x_e), y, w.tx, w.sy,
+                         reinterpret_cast<d2*>(grad_U), reinterpret_cast<d2*>(grad_N), s));
+    HIP_TRY(launch_redot(y, reinterpret_cast<const d2*>(x_e), lat.Vh, nrhs, -8.0 * mass, grad_m,
+                         w.red, w.cnt, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return st;
+}
+
+size_t hisq_batched_workspace_bytes(int nprob, const hisq_problem* probs, int mode)
+{
+    if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
+    if (check_problems(nprob, probs, mode)) return 0;
+    std::vector<Ws> ws;
+    CgState* st;
+    void* tab;
+    return batched_layout(nprob, probs, mode, nullptr, &ws, &st, &tab);
+}
+
+int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_params* p, void* ws,
+                          size_t ws_bytes, hisq_info* infos, void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    if (!p) return fail(HISQ_EINVAL, "params is NULL");
+    int rc = check_params(p, 1);
+    if (rc) return rc;
+    if ((rc = check_problems(nprob, probs, p->mode))) return rc;
+    if (!ws) return fail(HISQ_EINVAL, "workspace is NULL");
+    std::vector<Ws> w;
+    CgState* states;
+    void* table;
+    const size_t need = batched_layout(nprob, probs, p->mode, nullptr, &w, &states, &table);
+    if (ws_bytes < need)
+        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    batched_layout(nprob, probs, p->mode, reinterpret_cast<char*>(ws), &w, &states, &table);
+    Engine E;
+    E.prm = *p;
+    E.mixed = p->mode == HISQ_MODE_MIXED;
+    E.r14 = E.mixed && p->naik == HISQ_NAIK_R14;
+    E.s = reinterpret_cast<hipStream_t>(stream);
+    E.states = states;
+    E.table = table;
+    for (int j = 0; j < nprob; ++j) {
+        Prob q;
+        q.lat = make_lat(probs[j].geom);
+        q.n = probs[j].nrhs;
+        q.mass = probs[j].mass;
+        q.m4 = 4.0 * q.mass * q.mass;
+        q.links64 = probs[j].links64;
+        q.links32 = probs[j].links32;
+        q.b = reinterpret_cast<const d2*>(probs[j].b);
+        q.x = reinterpret_cast<d2*>(probs[j].x);
+        q.w = w[j];
+        E.P.push_back(q);
+    }
+    return E.run(infos);
+}
+
+int hisq_set_tuning(int mode, int rhs_per_thread, int block_size)
+{
+    if (mode < 0 || mode > 2) return fail(HISQ_EINVAL, "unknown tuning mode %d", mode);
+    if (mode == 1) {
+        if (rhs_per_thread < 1 || rhs_per_thread > HISQ_MAX_RHS)
+            return fail(HISQ_EINVAL, "rhs_per_thread must be in 1..8");
+        if (block_size != 64 && block_size != 128 && block_size != 256)
+            return fail(HISQ_EINVAL, "block_size must be 64, 128 or 256");
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_mode = mode;
+    g_force_nr = rhs_per_thread;
+    g_force_bs = block_size;
+    return HISQ_OK;
+}
+
+const char* hisq_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,420 @@
+// HISQ half-Dslash kernels for gfx950 (Sec. 1, eqs. (3) and (4)).
+//
+// One thread computes NR rhs of one output site; the G = n/NR threads of a
+// site are adjacent lanes, so their spinor loads are contiguous and their link
+// loads hit the same cache line.  Per output site the thread streams the 16
+// matrices of its parity block once (non-temporal loads: links have no reuse
+// within a half-Dslash) and gathers the 16 neighbour colour vectors of its rhs
+// tile; the neighbour vectors are re-read by up to 16 sites and are served from
+// L2 / Infinity Cache.  All accumulation is in the storage precision; the CG
+// dot products are accumulated in FP64.
+//
+// This file is compiled once per (precision, Naik storage, epilogue):
+//   HISQ_KPREC 0 = FP64, 1 = FP32, 2 = FP32 with r14 Naik links
+//   HISQ_KEPI  one of EPI_PLAIN, EPI_NORM, EPI_CG, EPI_RESID
+#include <type_traits>
+
+#include "hisq_device.h"
+
+#ifndef HISQ_KPREC
+#error "HISQ_KPREC must be defined"
+#endif
+#ifndef HISQ_KEPI
+#error "HISQ_KEPI must be defined"
+#endif
+
+namespace hisq {
+
+#if HISQ_KPREC == 0
+using KT = double;
+constexpr bool kR14 = false;
+#elif HISQ_KPREC == 1
+using KT = float;
+constexpr bool kR14 = false;
+#else
+using KT = float;
+constexpr bool kR14 = true;
+#endif
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b)
+{
+    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename C>
+__device__ __forceinline__ C cconj(C a)
+{
+    return C{a.x, -a.y};
+}
+
+// acc += m * v in four fused multiply-adds
+template <typename C>
+__device__ __forceinline__ void cfma(C& acc, C m, C v)
+{
+    acc.x = __builtin_fma(m.x, v.x, acc.x);
+    acc.x = __builtin_fma(-m.y, v.y, acc.x);
+    acc.y = __builtin_fma(m.x, v.y, acc.y);
+    acc.y = __builtin_fma(m.y, v.x, acc.y);
+}
+
+__device__ __forceinline__ int wrap_delta(int c, int h, int L)
+{
+    const int cp = c + h;
+    return h + (cp < 0 ? L : 0) - (cp >= L ? L : 0);
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Registers holding one slot's operands: the matrix and the neighbour's
+// colour vectors of this thread's rhs tile.
+template <typename T, int NR>
+struct SlotRegs {
+    cplx<T> m[9];
+    cplx<T> v[3][NR];
+};
+
+template <typename T, int NRHS, int NR, bool R14, int S>
+__device__ __forceinline__ void load_slot(const cplx<T>* __restrict__ lk,
+                                          const cplx<T>* __restrict__ in, int Vh, int i,
+                                          int nbr, int g, SlotRegs<T, NR>& o)
+{
+    using C = cplx<T>;
+    const C* lp = lk + link_slot_elem(S, R14) * Vh + i;
+    constexpr int ne = (R14 && S >= 8) ? 7 : 9;
+#pragma unroll
+    for (int e = 0; e < ne; ++e) o.m[e] = __builtin_nontemporal_load(lp + e * Vh);
+    const C* vp = in + (nbr * 3) * NRHS + g * NR;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + b * NRHS, o.v[b]);
+}
+
+template <typename T, int NR, bool R14, int S>
+__device__ __forceinline__ void apply_slot(SlotRegs<T, NR>& o, cplx<T> (&acc)[3][NR])
+{
+    if constexpr (R14 && S >= 8) {
+        // row 2 = c * conj(row0 x row1); c was loaded into m[6]
+        auto* m = o.m;
+        const cplx<T> cc = m[6];
+        m[6] = cmul(cc, cconj(cmul(m[1], m[5]) - cmul(m[2], m[4])));
+        m[7] = cmul(cc, cconj(cmul(m[2], m[3]) - cmul(m[0], m[5])));
+        m[8] = cmul(cc, cconj(cmul(m[0], m[4]) - cmul(m[1], m[3])));
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int k = 0; k < NR; ++k) cfma(acc[a][k], o.m[3 * a + b], o.v[b][k]);
+}
+
+// acc[c][k] = (D in)_{i}, colour c, rhs g*NR + k, output parity P.
+// Slot s = 4*hop + mu applies matrix s of the parity block to the neighbour
+// reached by hop (+1, -1, +3, -3) in direction mu.  The 16 slots run as a
+// two-stage pipeline: while slot s is multiplied, the matrix and neighbour
+// vectors of slot s+1 are in flight in the other register buffer.  The
+// scheduling barriers keep the compiler from hoisting further loads, which
+// would otherwise exhaust the register file.
+template <typename T, int NRHS, int NR, bool R14>
+__device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
+                                            const cplx<T>* __restrict__ lk,
+                                            const cplx<T>* __restrict__ in,
+                                            cplx<T> (&acc)[3][NR])
+{
+    using C = cplx<T>;
+    const int Vh = lat.Vh;
+    int r = i / lat.Lh0;
+    const int xh = i - r * lat.Lh0;
+    const int y = r % lat.L[1];
+    r /= lat.L[1];
+    const int z = r % lat.L[2];
+    const int t = r / lat.L[2];
+    const int x = 2 * xh + ((P + y + z + t) & 1);
+    const int row = i - xh;
+
+    int nb[16];
+    const int hops[4] = {1, -1, 3, -3};
+#pragma unroll
+    for (int hh = 0; hh < 4; ++hh) {
+        const int h = hops[hh];
+        const int xp = x + wrap_delta(x, h, lat.L[0]);
+        nb[4 * hh + 0] = row + (xp >> 1);
+        nb[4 * hh + 1] = i + wrap_delta(y, h, lat.L[1]) * lat.sy;
+        nb[4 * hh + 2] = i + wrap_delta(z, h, lat.L[2]) * lat.sz;
+        nb[4 * hh + 3] = i + wrap_delta(t, h, lat.L[3]) * lat.st;
+    }
+
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[c][k] = C{0, 0};
+
+    SlotRegs<T, NR> buf[2];
+    load_slot<T, NRHS, NR, R14, 0>(lk, in, Vh, i, nb[0], g, buf[0]);
+    static_for<0, 16>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        if constexpr (s + 1 < 16)
+            load_slot<T, NRHS, NR, R14, s + 1>(lk, in, Vh, i, nb[s + 1], g, buf[(s + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        apply_slot<T, NR, R14, s>(buf[s & 1], acc);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// An empty asm that reads every accumulator: keeps the compiler from sinking
+// the site's arithmetic into a later conditional block (past the loads of all
+// 16 slots, which would keep every loaded operand live at once).
+template <typename C, int NR>
+__device__ __forceinline__ void pin_acc(C (&acc)[3][NR])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) asm volatile("" ::"v"(acc[c][k].x), "v"(acc[c][k].y));
+}
+
+template <int EPI>
+__device__ __forceinline__ void finish(CgState* st, int k, double tot, double m4)
+{
+    if constexpr (EPI == EPI_NORM) {
+        // alpha = rr / <p, A p>, with <p, A p> = 4m^2 |p|^2 + |D_oe p|^2 (D_eo^dag = -D_oe)
+        st->tt[k] = tot;
+        if (st->active[k]) {
+            const double den = m4 * st->pp[k] + tot;
+            if (!(den > 0.0) || !finite_d(den)) {
+                st->status[k] = HISQ_BREAKDOWN;
+                st->active[k] = 0;
+                st->alpha[k] = 0.0;
+            } else {
+                st->alpha[k] = st->rr[k] / den;
+            }
+        } else {
+            st->alpha[k] = 0.0;
+        }
+    } else if constexpr (EPI == EPI_CG) {
+        if (st->active[k]) {
+            st->iters[k] += 1;
+            if (!finite_d(tot)) {
+                st->status[k] = HISQ_BREAKDOWN;
+                st->active[k] = 0;
+            } else {
+                st->beta[k] = tot / st->rr[k];
+                st->rr[k] = tot;
+                if (tot <= st->thresh[k] || st->iters[k] >= st->maxiter) st->active[k] = 0;
+            }
+        }
+    } else if constexpr (EPI == EPI_RESID) {
+        st->rr_true[k] = tot;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double norm2c(cplx<T> v)
+{
+    return (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+
+// One tile (one work-group's worth of sites) of a half-Dslash with epilogue
+// EPI; `tile` is the tile index, the problem's grid has nblk work-groups and
+// this one is number bid (for the reductions).
+template <typename T, int NRHS, int NR, bool R14, int EPI>
+__device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, int nblk, int bid)
+{
+    using C = cplx<T>;
+    constexpr int G = NRHS / NR;
+    if constexpr (EPI == EPI_NORM || EPI == EPI_CG) {
+        // every rhs of the bundle converged: the iteration is a no-op
+        bool any_prob = false;
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) any_prob = any_prob || (a.state->active[k] != 0);
+        if (!any_prob) return;
+    }
+    const int g = threadIdx.x % G;
+    double part[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) part[k] = 0.0;
+
+    bool act[NR];
+    T alpha[NR];
+    bool any_act = false;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        act[k] = false;
+        alpha[k] = T(0);
+        if constexpr (EPI == EPI_CG) {
+            act[k] = a.state->active[g * NR + k] != 0;
+            alpha[k] = act[k] ? (T)a.state->alpha[g * NR + k] : T(0);
+        } else if constexpr (EPI == EPI_RESID) {
+            act[k] = a.state->sel[g * NR + k] != 0;
+        }
+        any_act = any_act || act[k];
+    }
+    const T m4 = (T)a.mass4;
+
+    const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
+    if (i < a.lat.Vh) {
+        C acc[3][NR];
+        dslash_site<T, NRHS, NR, R14>(a.lat, a.parity, i, g, a.links, a.in, acc);
+        pin_acc(acc);
+        const int base = i * 3 * NRHS + g * NR;
+        if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                store_rhs<NR>(a.out + base + c * NRHS, acc[c]);
+                if constexpr (EPI == EPI_NORM) {
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) part[k] += norm2c<T>(acc[c][k]);
+                }
+            }
+        } else if constexpr (EPI == EPI_CG) {
+            if (any_act) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                C pv[NR], xv[NR], rv[NR];
+                load_rhs<NR>(a.p + base + c * NRHS, pv);
+                load_rhs<NR>(a.x + base + c * NRHS, xv);
+                load_rhs<NR>(a.r + base + c * NRHS, rv);
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const C q = C{m4 * pv[k].x - acc[c][k].x, m4 * pv[k].y - acc[c][k].y};
+                    if (act[k]) {
+                        xv[k] = C{xv[k].x + alpha[k] * pv[k].x, xv[k].y + alpha[k] * pv[k].y};
+                        rv[k] = C{rv[k].x - alpha[k] * q.x, rv[k].y - alpha[k] * q.y};
+                    }
+                    part[k] += norm2c<T>(rv[k]);
+                }
+                store_rhs<NR>(a.x + base + c * NRHS, xv);
+                store_rhs<NR>(a.r + base + c * NRHS, rv);
+            }
+            }
+        } else if constexpr (EPI == EPI_RESID) {
+            if (any_act) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d2 bv[NR], xv[NR];
+                load_rhs<NR>(a.b + base + c * NRHS, bv);
+                load_rhs<NR>(a.xh + base + c * NRHS, xv);
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const d2 rv = d2{bv[k].x - (m4 * xv[k].x - acc[c][k].x),
+                                     bv[k].y - (m4 * xv[k].y - acc[c][k].y)};
+                    part[k] += norm2c<double>(rv);
+                    if (act[k]) a.out[base + c * NRHS + k] = rv;
+                }
+            }
+            }
+        }
+    }
+
+    if constexpr (EPI != EPI_PLAIN) {
+        double total;
+        if (grid_reduce_rhs<NRHS, NR>(part, a.red, a.cnt, nblk, bid, &total)) {
+            if (threadIdx.x < NRHS) finish<EPI>(a.state, threadIdx.x, total, a.mass4);
+        }
+    }
+}
+
+template <typename T, int NRHS, int NR, bool R14, int EPI>
+__global__ __launch_bounds__(kMaxBlock) void k_dslash(const DslashArgs<T> a)
+{
+    dslash_tile<T, NRHS, NR, R14, EPI>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap), gridDim.x,
+                                       blockIdx.x);
+}
+
+// Batched form: one launch covers the tiles of every problem of a BatchTable;
+// each work-group finds its problem (uniform scalar search over <= 16 entries)
+// and runs the body specialised for that problem's bundle size and tile.
+template <typename T, bool R14, int EPI>
+__global__ __launch_bounds__(kMaxBlock) void k_dslash_batched(const BatchTable<T>* __restrict__ tab)
+{
+    int q = 0;
+    for (int j = 1; j < tab->nprob; ++j)
+        if ((int)blockIdx.x >= tab->p[j].block_start) q = j;
+    const BatchProb<T>& bp = tab->p[q];
+    const int bid = (int)blockIdx.x - bp.block_start;
+    if (bid >= bp.nblocks) return;
+    const DslashArgs<T>& a = EPI == EPI_NORM ? bp.k2 : bp.k3;
+    const int nb = bp.nblocks;
+    switch (bp.n * 16 + bp.nr) {
+    case 1 * 16 + 1: dslash_tile<T, 1, 1, R14, EPI>(a, bid, nb, bid); break;
+    case 2 * 16 + 2: dslash_tile<T, 2, 2, R14, EPI>(a, bid, nb, bid); break;
+    case 2 * 16 + 1: dslash_tile<T, 2, 1, R14, EPI>(a, bid, nb, bid); break;
+    case 3 * 16 + 3: dslash_tile<T, 3, 3, R14, EPI>(a, bid, nb, bid); break;
+    case 4 * 16 + 4: dslash_tile<T, 4, 4, R14, EPI>(a, bid, nb, bid); break;
+    case 4 * 16 + 2: dslash_tile<T, 4, 2, R14, EPI>(a, bid, nb, bid); break;
+    case 5 * 16 + 5: dslash_tile<T, 5, 5, R14, EPI>(a, bid, nb, bid); break;
+    case 6 * 16 + 6: dslash_tile<T, 6, 6, R14, EPI>(a, bid, nb, bid); break;
+    case 6 * 16 + 3: dslash_tile<T, 6, 3, R14, EPI>(a, bid, nb, bid); break;
+    case 7 * 16 + 7: dslash_tile<T, 7, 7, R14, EPI>(a, bid, nb, bid); break;
+    case 8 * 16 + 8: dslash_tile<T, 8, 8, R14, EPI>(a, bid, nb, bid); break;
+    case 8 * 16 + 4: dslash_tile<T, 8, 4, R14, EPI>(a, bid, nb, bid); break;
+    default: break;
+    }
+}
+
+template <typename T, bool R14, int EPI, int NRHS, int NR>
+static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s)
+{
+    constexpr int G = NRHS / NR;
+    const long threads = (long)a.lat.Vh * G;
+    a.ntiles = (int)((threads + t.bs - 1) / t.bs);
+    a.remap = t.remap;
+    hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool R14, int EPI, int NRHS>
+static hipError_t pick_nr(const Tile& t, const DslashArgs<T>& a, hipStream_t s)
+{
+    if (t.nr == NRHS) return go<T, R14, EPI, NRHS, NRHS>(t, a, s);
+    if constexpr (NRHS % 2 == 0)
+        if (t.nr == NRHS / 2) return go<T, R14, EPI, NRHS, NRHS / 2>(t, a, s);
+    if constexpr (NRHS % 4 == 0)
+        if (t.nr == NRHS / 4) return go<T, R14, EPI, NRHS, NRHS / 4>(t, a, s);
+    if constexpr (NRHS % 8 == 0)
+        if (t.nr == NRHS / 8) return go<T, R14, EPI, NRHS, NRHS / 8>(t, a, s);
+    return hipErrorInvalidValue;
+}
+
+#define HISQ_CAT2(a, b) a##b
+#define HISQ_CAT(a, b) HISQ_CAT2(a, b)
+#define HISQ_LAUNCH_NAME HISQ_CAT(HISQ_CAT(HISQ_CAT(launch_dslash_p, HISQ_KPREC), _e), HISQ_KEPI)
+
+hipError_t HISQ_LAUNCH_NAME(int nrhs, const Tile& t, const DslashArgs<KT>& a, hipStream_t s)
+{
+    constexpr int EPI = HISQ_KEPI;
+    if constexpr (EPI == EPI_RESID && HISQ_KPREC != 0) {
+        return hipErrorInvalidValue;
+    } else {
+        switch (nrhs) {
+        case 1: return pick_nr<KT, kR14, EPI, 1>(t, a, s);
+        case 2: return pick_nr<KT, kR14, EPI, 2>(t, a, s);
+        case 3: return pick_nr<KT, kR14, EPI, 3>(t, a, s);
+        case 4: return pick_nr<KT, kR14, EPI, 4>(t, a, s);
+        case 5: return pick_nr<KT, kR14, EPI, 5>(t, a, s);
+        case 6: return pick_nr<KT, kR14, EPI, 6>(t, a, s);
+        case 7: return pick_nr<KT, kR14, EPI, 7>(t, a, s);
+        case 8: return pick_nr<KT, kR14, EPI, 8>(t, a, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+#if HISQ_KEPI == 1 || HISQ_KEPI == 2
+#define HISQ_BNAME HISQ_CAT(HISQ_CAT(HISQ_CAT(launch_dslash_batched_p, HISQ_KPREC), _e), HISQ_KEPI)
+hipError_t HISQ_BNAME(const BatchTable<KT>* tab, int total_blocks, int bs, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_dslash_batched<KT, kR14, HISQ_KEPI>), dim3(total_blocks), dim3(bs), 0, s,
+                       tab);
+    return hipGetLastError();
+}
+#endif
+
+}  // namespace hisq

@@ -1,0 +1,197 @@
+// Device helpers shared by the HIP kernels: tile scheduling and the per-rhs
+// FP64 reductions of the CG dot products.
+#pragma once
+
+#include "hisq_internal.h"
+
+namespace hisq {
+
+// Work-group -> tile map.  Work-groups are dealt to the 8 XCDs of the chip
+// round-robin (work-group b starts on XCD b mod 8).  With `remap` set, the
+// tiles are split into 8 contiguous ranges and XCD j walks range j in order, so
+// each XCD's L2 sees a contiguous slab of the lattice and the stencil's
+// neighbours are mostly resident in the same L2.  A bijection on [0, gridDim).
+__device__ inline int tile_of_block(int b, int nb, int remap)
+{
+    if (!remap || nb < 8) return b;
+    const int j = b & 7, m = b >> 3;
+    const int q = nb >> 3, rem = nb & 7;
+    return j * q + (j < rem ? j : rem) + m;
+}
+
+__device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+
+constexpr int kRedGroup = 64;  // work-groups per second-stage group
+
+// Coherent accesses for the cross-work-group reduction.  Plain stores stay in
+// the L2 of the XCD that wrote them; agent-scope atomic accesses are performed
+// at the device-coherent level, so a work-group on another XCD sees them.
+// (No release fence is used: on this chip an agent-scope release writes back
+// the whole L2, far too costly once per work-group.)
+__device__ __forceinline__ void store_coherent(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_coherent(const double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_coherent(uint32_t* p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until this wave's outstanding memory operations have completed, i.e.
+// its coherent stores have been performed, before it signals a counter.
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Sum over all 64 lanes by an xor butterfly: every lane ends with the same,
+// bitwise identical total (each step adds the same two values).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += shfl_xor_d(v, off);
+    return v;
+}
+
+// Per-rhs FP64 sums over the whole grid, in a fixed order (bitwise
+// reproducible, no floating-point atomics).  Each thread contributes part[k]
+// to rhs g*NR + k, where g = lane mod G is its rhs group.
+//   stage 1: wave butterflies + LDS -> one partial per work-group and rhs;
+//   stage 2: the last work-group of each group of 64 (atomic counter) sums the
+//            group's partials;
+//   stage 3: the last group to finish sums the group sums.
+// Only wave 0 of a work-group takes part after stage 1.  Returns true in wave 0
+// of the one work-group that finished last; lane k < NRHS then holds the total
+// of rhs k in *total.  The grid is the nblk work-groups of one problem, this
+// one being number bid.  red: [nblk][NRHS] partials then [ngroups][NRHS] group
+// sums; cnt: [1 + ngroups] counters, zero on entry and re-armed on exit.
+template <int NRHS, int NR>
+__device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, int nblk, int bid,
+                                double* total)
+{
+    constexpr int G = NRHS / NR;
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "rhs groups must be a power of two");
+    __shared__ double sred[kMaxBlock / 64][kMaxRhs];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+    const int ngroups = (nblk + kRedGroup - 1) / kRedGroup;
+    double* gsum = red + (size_t)nblk * NRHS;
+
+    // stage 1
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+#pragma unroll
+        for (int off = 32; off >= G; off >>= 1) part[k] += shfl_xor_d(part[k], off);
+    }
+    if (lane < G) {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) sred[wave][lane * NR + k] = part[k];
+    }
+    __syncthreads();
+    if (wave != 0) return false;
+    if (lane < NRHS) {
+        double s = 0;
+        for (int w = 0; w < nwaves; ++w) s += sred[w][lane];
+        store_coherent(&red[(size_t)bid * NRHS + lane], s);
+    }
+    wait_memory();
+    const int grp = bid / kRedGroup;
+    const int g0 = grp * kRedGroup;
+    const int gn = min(kRedGroup, nblk - g0);
+    uint32_t prev = 0;
+    if (lane == 0) prev = add_coherent(&cnt[1 + grp], 1u);
+    prev = __shfl(prev, 0, 64);
+    if (prev != (uint32_t)(gn - 1)) return false;
+
+    // stage 2: the last work-group of the group
+    double acc[NRHS];
+    const double* row = &red[(size_t)(g0 + (lane < gn ? lane : 0)) * NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) acc[k] = load_coherent(row + k);  // all loads in flight
+    double mine = 0;
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        acc[k] = wave_sum(lane < gn ? acc[k] : 0.0);
+        if (lane == k) mine = acc[k];
+    }
+    if (lane < NRHS) store_coherent(&gsum[(size_t)grp * NRHS + lane], mine);
+    if (lane == 0) store_coherent(&cnt[1 + grp], 0u);
+    wait_memory();
+    if (lane == 0) prev = add_coherent(&cnt[0], 1u);
+    prev = __shfl(prev, 0, 64);
+    if (prev != (uint32_t)(ngroups - 1)) return false;
+
+    // stage 3: the last group
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) acc[k] = 0.0;
+    for (int j = lane; j < ngroups; j += 64) {
+        double v[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) v[k] = load_coherent(&gsum[(size_t)j * NRHS + k]);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) acc[k] += v[k];
+    }
+    mine = 0;
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        acc[k] = wave_sum(acc[k]);
+        if (lane == k) mine = acc[k];
+    }
+    if (lane == 0) store_coherent(&cnt[0], 0u);
+    *total = mine;
+    return true;
+}
+
+__device__ inline bool finite_d(double v) { return v - v == 0.0; }
+
+// Loads and stores of NR consecutive complex numbers (rhs of one colour).
+template <int NR>
+__device__ __forceinline__ void load_rhs(const f2* __restrict__ p, f2 (&v)[NR])
+{
+    if constexpr (NR % 2 == 0) {
+        const f4* q = reinterpret_cast<const f4*>(p);
+#pragma unroll
+        for (int k = 0; k < NR / 2; ++k) {
+            f4 w = q[k];
+            v[2 * k] = f2{w.x, w.y};
+            v[2 * k + 1] = f2{w.z, w.w};
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) v[k] = p[k];
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void load_rhs(const d2* __restrict__ p, d2 (&v)[NR])
+{
+#pragma unroll
+    for (int k = 0; k < NR; ++k) v[k] = p[k];
+}
+
+template <int NR>
+__device__ __forceinline__ void store_rhs(f2* __restrict__ p, const f2 (&v)[NR])
+{
+    if constexpr (NR % 2 == 0) {
+        f4* q = reinterpret_cast<f4*>(p);
+#pragma unroll
+        for (int k = 0; k < NR / 2; ++k) q[k] = f4{v[2 * k].x, v[2 * k].y, v[2 * k + 1].x, v[2 * k + 1].y};
+    } else {
+#pragma unroll
+        for (int k = 0; k < NR; ++k) p[k] = v[k];
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void store_rhs(d2* __restrict__ p, const d2 (&v)[NR])
+{
+#pragma unroll
+    for (int k = 0; k < NR; ++k) p[k] = v[k];
+}
+
+}  // namespace hisq

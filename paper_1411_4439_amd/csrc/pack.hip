@@ -1,0 +1,127 @@
+// Link packing: canonical [4][V][3][3] complex128 U, N -> the per-parity slot
+// blocks the Dslash kernels stream (layout described in hisq_internal.h).
+//
+// For output site z the 16 slots are U_{z,mu}, -U^dag_{z-mu,mu}, N_{z,mu} and
+// -N^dag_{z-3mu,mu} (the four terms of Sec. 1 eq. (3), sign folded in).  In r14
+// storage a Naik slot keeps rows 0 and 1 and c = <w, row2> / |w|^2 with
+// w = conj(row0 x row1), so that row2 = c w exactly when the matrix is a
+// positive multiple of a U(3) matrix; the worst relative round-trip error is
+// kept in the buffer header (atomicMax on the float's bits, valid for
+// non-negative floats).
+#include "hisq_device.h"
+
+namespace hisq {
+
+__device__ __forceinline__ d2 cmul_d(d2 a, d2 b)
+{
+    return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+__device__ __forceinline__ int site_of(const Lat& lat, const int x[4])
+{
+    return x[0] + lat.L[0] * (x[1] + lat.L[1] * (x[2] + lat.L[2] * x[3]));
+}
+
+template <typename T, bool R14>
+__global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__ N,
+                       cplx<T>* __restrict__ out, LinkHeader* hdr)
+{
+    using C = cplx<T>;
+    const int Vh = lat.Vh;
+    const int V = 2 * Vh;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= V) return;
+    const int P = idx / Vh;
+    const int i = idx - P * Vh;
+    int r = i / lat.Lh0;
+    const int xh = i - r * lat.Lh0;
+    int c[4];
+    c[1] = r % lat.L[1];
+    r /= lat.L[1];
+    c[2] = r % lat.L[2];
+    c[3] = r / lat.L[2];
+    c[0] = 2 * xh + ((P + c[1] + c[2] + c[3]) & 1);
+    const int s = site_of(lat, c);
+    C* blk = out + (size_t)P * link_block_elems(Vh, R14);
+    float worst = 0.0f;
+    for (int slot = 0; slot < 16; ++slot) {
+        const int mu = slot & 3, kind = slot >> 2;  // 0: U fwd, 1: U bwd, 2: N fwd, 3: N bwd
+        const d2* W = (kind < 2) ? U : N;
+        int root = s;
+        if (kind == 1 || kind == 3) {
+            int y[4] = {c[0], c[1], c[2], c[3]};
+            const int h = kind == 1 ? 1 : 3;
+            y[mu] = (y[mu] - h + lat.L[mu]) % lat.L[mu];
+            root = site_of(lat, y);
+        }
+        const d2* src = W + ((size_t)mu * V + root) * 9;
+        d2 m[9];
+        for (int e = 0; e < 9; ++e) m[e] = src[e];
+        if (kind == 1 || kind == 3) {  // -W^dag
+            d2 t[9];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) t[3 * a + b] = d2{-m[3 * b + a].x, m[3 * b + a].y};
+            for (int e = 0; e < 9; ++e) m[e] = t[e];
+        }
+        C* dst = blk + (size_t)link_slot_elem(slot, R14) * Vh + i;
+        if (R14 && slot >= 8) {
+            // w = conj(row0 x row1); c = <w, row2> / |w|^2
+            d2 w[3];
+            w[0] = cmul_d(m[1], m[5]) - cmul_d(m[2], m[4]);
+            w[1] = cmul_d(m[2], m[3]) - cmul_d(m[0], m[5]);
+            w[2] = cmul_d(m[0], m[4]) - cmul_d(m[1], m[3]);
+            for (int j = 0; j < 3; ++j) w[j].y = -w[j].y;
+            d2 num = d2{0, 0};
+            double den = 0, fro = 0, err = 0;
+            for (int j = 0; j < 3; ++j) {
+                num += cmul_d(d2{w[j].x, -w[j].y}, m[6 + j]);
+                den += w[j].x * w[j].x + w[j].y * w[j].y;
+            }
+            const d2 cc = den > 0 ? d2{num.x / den, num.y / den} : d2{0, 0};
+            for (int e = 0; e < 9; ++e) fro += m[e].x * m[e].x + m[e].y * m[e].y;
+            for (int j = 0; j < 3; ++j) {
+                const d2 d = m[6 + j] - cmul_d(cc, w[j]);
+                err += d.x * d.x + d.y * d.y;
+            }
+            const double rel = fro > 0 ? sqrt(err / fro) : 0.0;
+            const float relf = (rel == rel) ? (float)rel : 3.0e38f;
+            worst = fmaxf(worst, relf);
+            for (int e = 0; e < 6; ++e) dst[(size_t)e * Vh] = C{(T)m[e].x, (T)m[e].y};
+            dst[(size_t)6 * Vh] = C{(T)cc.x, (T)cc.y};
+        } else {
+            for (int e = 0; e < 9; ++e) dst[(size_t)e * Vh] = C{(T)m[e].x, (T)m[e].y};
+        }
+    }
+    if (R14 && worst > 0.0f) atomicMax(&hdr->r14_err_bits, __float_as_uint(worst));
+}
+
+__global__ void k_pack_header(LinkHeader h, LinkHeader* dst) { *dst = h; }
+
+hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int naik, void* packed,
+                       hipStream_t s)
+{
+    LinkHeader h{};
+    h.magic = kLinkMagic;
+    for (int mu = 0; mu < 4; ++mu) h.L[mu] = lat.L[mu];
+    h.prec = prec;
+    h.naik = naik;
+    h.r14_err_bits = 0u;
+    LinkHeader* hdr = reinterpret_cast<LinkHeader*>(packed);
+    hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, s, h, hdr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    char* body = reinterpret_cast<char*>(packed) + kLinkHeaderBytes;
+    const int V = 2 * lat.Vh, bs = 128, grid = (V + bs - 1) / bs;
+    if (prec == HISQ_PREC_F64)
+        hipLaunchKernelGGL((k_pack<double, false>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<d2*>(body), hdr);
+    else if (naik == HISQ_NAIK_R14)
+        hipLaunchKernelGGL((k_pack<float, true>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<f2*>(body), hdr);
+    else
+        hipLaunchKernelGGL((k_pack<float, false>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<f2*>(body), hdr);
+    return hipGetLastError();
+}
+
+}  // namespace hisq

@@ -1,0 +1,130 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/hisq.h declares, and its host-only logic (size queries, argument and
+geometry checks) behaves as documented.  No call here launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hisq.h")
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1411_4439_amd import hisq
+    return hisq
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(hisq_[a-z0-9_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("hisq_dslash", "hisq_cg_solve", "hisq_cg_solve_backward",
+                     "hisq_cg_solve_batched", "hisq_pack_links", "hisq_links_bytes",
+                     "hisq_workspace_bytes", "hisq_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(H):
+    lib = ctypes.CDLL(H.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(_declared_functions()) == set(H.EXPORTS)
+
+
+def test_struct_layouts_match_header(H):
+    # sizes follow the C declarations (natural alignment)
+    assert ctypes.sizeof(H.Geom) == 16
+    assert ctypes.sizeof(H.Params) == 48
+    assert ctypes.sizeof(H.Problem) == 16 + 8 + 8 + 4 * 8
+    assert ctypes.sizeof(H.Info) == 8 * 4 * 2 + 8 * 8 * 2 + 5 * 4 + 4 + 8 + 4 * 8 + 4 * 4
+
+
+def test_default_params(H):
+    p = H.hisq_default_params()
+    assert p.mode == H.MODE_FP64 and p.tol == 1e-10 and p.maxiter == 20000
+    assert p.delta == 0.1 and p.use_graph == 1 and p.use_x0 == 0
+
+
+def test_links_bytes(H):
+    L = (8, 8, 8, 8)
+    Vh = 8 ** 4 // 2
+    assert H.hisq_links_bytes(L, H.PREC_F64, H.NAIK_FULL) == 256 + 2 * 144 * Vh * 16
+    assert H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_FULL) == 256 + 2 * 144 * Vh * 8
+    assert H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_R14) == 256 + 2 * 128 * Vh * 8
+    # r14 is an FP32 format; odd or small extents are rejected
+    assert H.hisq_links_bytes(L, H.PREC_F64, H.NAIK_R14) == 0
+    assert H.hisq_links_bytes((8, 8, 8, 7), H.PREC_F64, H.NAIK_FULL) == 0
+    assert H.hisq_links_bytes((2, 8, 8, 8), H.PREC_F64, H.NAIK_FULL) == 0
+
+
+def test_workspace_bytes(H):
+    L = (8, 8, 8, 8)
+    w64 = H.hisq_workspace_bytes(L, 4, H.MODE_FP64)
+    wmx = H.hisq_workspace_bytes(L, 4, H.MODE_MIXED)
+    Vh = 8 ** 4 // 2
+    assert w64 >= 3 * Vh * 3 * 4 * 16
+    assert wmx >= 2 * Vh * 3 * 4 * 16 + 4 * Vh * 3 * 4 * 8
+    assert H.hisq_backward_workspace_bytes(L, 4, H.MODE_FP64) >= w64 + 3 * Vh * 3 * 4 * 16
+    assert H.hisq_workspace_bytes(L, 0, H.MODE_FP64) == 0
+    assert H.hisq_workspace_bytes(L, 9, H.MODE_FP64) == 0
+    assert H.hisq_workspace_bytes(L, 1, 7) == 0
+
+
+def test_errors_before_any_launch(H):
+    """Invalid calls return a negative code and a message without touching a GPU."""
+    lib = H._lib
+    g = H.geom((8, 8, 8, 6))
+    bad = H.geom((8, 8, 5, 6))
+    p = H.hisq_default_params()
+    info = H.Info()
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.hisq_cg_solve(ctypes.byref(bad), 0.1, 1, ctypes.byref(p), fake, None, fake, fake,
+                           fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EGEOM and "L[2]" in H.hisq_last_error()
+    rc = lib.hisq_cg_solve(ctypes.byref(g), 0.1, 9, ctypes.byref(p), fake, None, fake, fake,
+                           fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL
+    p.tol = 0.0
+    rc = lib.hisq_cg_solve(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, fake, fake,
+                           fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL
+    p = H.hisq_default_params(mode=H.MODE_MIXED)
+    rc = lib.hisq_cg_solve(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, fake, fake,
+                           fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL and "FP32" in H.hisq_last_error()
+    p = H.hisq_default_params()
+    rc = lib.hisq_cg_solve(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, fake, fake,
+                           fake, 16, ctypes.byref(info), None)
+    assert rc == H.HISQ_EWORKSPACE
+    rc = lib.hisq_dslash(ctypes.byref(g), 2, 1, H.PREC_F64, H.NAIK_FULL, fake, fake, fake, None)
+    assert rc == H.HISQ_EINVAL
+    rc = lib.hisq_pack_links(ctypes.byref(g), fake, fake, H.PREC_F64, H.NAIK_R14, fake, None)
+    assert rc == H.HISQ_EINVAL
+    rc = lib.hisq_cg_solve_batched(0, None, ctypes.byref(p), fake, 0, None, None)
+    assert rc == H.HISQ_EINVAL
+
+
+def test_tuning_control(H):
+    assert H.hisq_set_tuning(2) == 0
+    with pytest.raises(H.HisqError):
+        H.hisq_set_tuning(1, 3, 100)
+    with pytest.raises(H.HisqError):
+        H.hisq_set_tuning(5)
+    assert H.hisq_set_tuning(0) == 0
+
+
+def test_solver_refuses_host_tensors(H):
+    import torch
+    L = (4, 4, 4, 4)
+    b = torch.zeros((128, 3, 1), dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        H.hisq_dslash(L, 0, 1, H.PREC_F64, H.NAIK_FULL, torch.zeros(16, dtype=torch.uint8), b, b)

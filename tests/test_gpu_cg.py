@@ -1,0 +1,210 @@
+"""GPU even-odd CG against the FP64 CPU oracle.
+
+Gates: the true residual ||b - A x|| / ||b|| of the GPU solution, recomputed by
+the oracle in FP64, is <= 1e-10 (the solver's tolerance); the solution matches
+the oracle's (tol 1e-13) or LAPACK's within 1e-8, or within the a-posteriori
+bound ||x - x*|| <= ||b - A x|| / (4 m^2) where the conditioning allows no more.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense
+from paper_1411_4439_amd import workload as W
+from tests.gpu_util import dev, gpu_lib, host, rel_l2_per_rhs, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(H, L, eps, seed, n, sseed):
+    U, N = W.make_links(L, eps, seed)
+    links = H.Links(L, dev(U), dev(N))
+    b = W.make_sources(L, n, sseed)
+    return U, N, links, b
+
+
+def _check_solution(L, U, N, m, b, x, x_ref, tol=1e-10):
+    res = oracle.residual(L, U, N, m, b, x)
+    assert res.max() <= tol * 1.0001, res
+    for k in range(b.shape[2]):
+        err = np.linalg.norm(x[..., k] - x_ref[..., k]) / np.linalg.norm(x_ref[..., k])
+        bound = res[k] * np.linalg.norm(b[..., k]) / (4 * m * m) / np.linalg.norm(x_ref[..., k])
+        assert err <= max(1e-8, 2 * bound), (k, err, bound)
+
+
+def test_config1_fp64_8x4():
+    """8^4, m = 0.1, one rhs, plain FP64, stop at 1e-10."""
+    H = gpu_lib()
+    L, m = (8, 8, 8, 8), 0.1
+    U, N, links, b = _setup(H, L, 0.3, W.links_seed(1), 1, W.sources_seed(1))
+    x, status, info = H.solve(links, m, dev(b))
+    say(info)
+    assert status == H.HISQ_OK
+    xo, oinfo = oracle.cg(L, U, N, m, b, tol=1e-13)
+    _check_solution(L, U, N, m, b, host(x), xo)
+    # same method, same stopping rule: iteration counts agree closely
+    _, o10 = oracle.cg(L, U, N, m, b, tol=1e-10)
+    assert abs(info["iters"][0] - o10["iters"][0]) <= 0.05 * o10["iters"][0] + 3
+
+
+@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14")])
+@pytest.mark.parametrize("n", [1, 3, 4, 8])
+def test_bundles_vs_lapack(mode, naik, n):
+    """4^4 (wrap aliasing): every rhs against LAPACK's dense solve."""
+    H = gpu_lib()
+    L, m = (4, 4, 4, 4), 0.05
+    U, N, links, b = _setup(H, L, 0.3, 21, n, 22 + n)
+    md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
+    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_FULL
+    x, status, info = H.solve(links, m, dev(b), mode=md, naik=nk)
+    say(mode, naik, n, info["iters"], info["reliable_updates"])
+    assert status == H.HISQ_OK
+    A = dense.even_normal_matrix(L, U, N, m)
+    xd = np.linalg.solve(A, b.reshape(-1, n)).reshape(b.shape)
+    _check_solution(L, U, N, m, b, host(x), xd)
+    if mode == "mixed":
+        assert info["reliable_updates"] >= 1
+
+
+@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14")])
+def test_medium_lattice_small_mass(mode, naik):
+    """16^3 x 4 (ragged tiles in every tile shape), m = 0.01, n = 5."""
+    H = gpu_lib()
+    L, m, n = (16, 16, 16, 4), 0.01, 5
+    U, N, links, b = _setup(H, L, 0.3, 31, n, 32)
+    md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
+    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_FULL
+    x, status, info = H.solve(links, m, dev(b), mode=md, naik=nk)
+    say(mode, naik, info["iters"], info["reliable_updates"], info["rel_true_res"])
+    assert status == H.HISQ_OK
+    res = oracle.residual(L, U, N, m, b, host(x))
+    assert res.max() <= 1e-10
+    assert np.allclose(res, info["rel_true_res"], rtol=1e-3, atol=1e-14)
+
+
+def test_mixed_matches_fp64_solution():
+    H = gpu_lib()
+    L, m, n = (8, 8, 8, 4), 0.02, 8
+    U, N, links, b = _setup(H, L, 0.3, 41, n, 42)
+    x64, s1, i1 = H.solve(links, m, dev(b), mode=H.MODE_FP64, tol=1e-12)
+    xmx, s2, i2 = H.solve(links, m, dev(b), mode=H.MODE_MIXED, tol=1e-12)
+    assert s1 == s2 == H.HISQ_OK
+    assert rel_l2_per_rhs(host(xmx), host(x64)) <= 1e-8
+
+
+def test_deterministic_and_graph_equals_stream():
+    """Fixed-order FP64 reductions: repeated solves are bitwise identical, and
+    the hipGraph path gives the same bits as plain stream launches."""
+    H = gpu_lib()
+    L, m, n = (8, 8, 8, 8), 0.05, 4
+    U, N, links, b = _setup(H, L, 0.3, 51, n, 52)
+    bd = dev(b)
+    for mode in (H.MODE_FP64, H.MODE_MIXED):
+        xa, _, _ = H.solve(links, m, bd, mode=mode)
+        xb, _, _ = H.solve(links, m, bd, mode=mode)
+        xc, _, _ = H.solve(links, m, bd, mode=mode, use_graph=0)
+        assert np.array_equal(host(xa), host(xb))
+        assert np.array_equal(host(xa), host(xc))
+
+
+def test_profile_counts_launches():
+    H = gpu_lib()
+    L, m, n = (8, 8, 8, 4), 0.1, 2
+    U, N, links, b = _setup(H, L, 0.3, 61, n, 62)
+    for g in (1, 0):
+        x, status, info = H.solve(links, m, dev(b), mode=H.MODE_MIXED, profile=1, use_graph=g)
+        assert status == H.HISQ_OK
+        launches = info["kernel_launches"]
+        # a profiled solve runs without a graph; every iteration is timed
+        assert launches[H.K_DSLASH_OE] == launches[H.K_DSLASH_EO] >= max(info["iters"])
+        assert all(t > 0 for t in info["kernel_ms"][:3])
+        assert launches[H.K_RELIABLE] == info["reliable_updates"] >= 1
+
+
+def test_start_vector_zero_source_and_maxiter():
+    H = gpu_lib()
+    L, m = (4, 4, 4, 6), 0.1
+    U, N, links, b = _setup(H, L, 0.3, 71, 3, 72)
+    b[..., 1] = 0
+    x0 = W.make_sources(L, 3, 73)  # non-zero start, also for the zero rhs
+    x, status, info = H.solve(links, m, dev(b), x0=dev(x0))
+    assert status == H.HISQ_OK
+    xh = host(x)
+    assert not np.any(xh[..., 1]), "b = 0 must give x = 0"
+    assert oracle.residual(L, U, N, m, b, xh)[[0, 2]].max() <= 1e-10
+    # restarting from the solution needs no iteration
+    x2, status, info = H.solve(links, m, dev(b), x0=x)
+    assert status == H.HISQ_OK and max(info["iters"]) == 0
+    # maxiter cap: reported, and x is the last iterate
+    x3, status, info = H.solve(links, m, dev(b), maxiter=5)
+    assert status == H.HISQ_NOT_CONVERGED
+    assert info["iters"][0] <= 5 and info["status"][0] == H.HISQ_NOT_CONVERGED
+    assert info["status"][1] == H.HISQ_OK
+
+
+def test_failure_paths_end_cleanly():
+    """Singular and non-finite inputs end with a positive status, never a hang."""
+    H = gpu_lib()
+    L = (4, 4, 4, 4)
+    U, N = W.free_links(L, 1.0)
+    links = H.Links(L, dev(U), dev(N))
+    b = W.to_half(W.plane_wave(L, (0, 0, 0, 0), [1.0, 0, 0]), L, 0)
+    for mode in (H.MODE_FP64, H.MODE_MIXED):
+        x, status, info = H.solve(links, 0.0, dev(b), mode=mode, maxiter=200)
+        assert status in (H.HISQ_BREAKDOWN, H.HISQ_NOT_CONVERGED)
+    U, N = W.make_links(L, 0.3, 81)
+    links = H.Links(L, dev(U), dev(N))
+    bn = W.make_sources(L, 2, 82)
+    bn[3, 1, 0] = np.nan
+    x, status, info = H.solve(links, 0.1, dev(bn), maxiter=100)
+    assert status > 0 and info["status"][0] > 0
+
+
+def test_batched_equals_separate_solves():
+    """Several lattices, masses and bundle sizes in one batched launch per phase."""
+    H = gpu_lib()
+    import torch
+    specs = [((8, 8, 8, 4), 3, 0.05), ((6, 6, 6, 4), 5, 0.01), ((8, 8, 4, 4), 8, 0.05),
+             ((4, 4, 4, 4), 1, 0.1)]
+    for mode, naik in ((H.MODE_MIXED, H.NAIK_FULL), (H.MODE_MIXED, H.NAIK_R14),
+                       (H.MODE_FP64, H.NAIK_FULL)):
+        probs, keep, refs = [], [], []
+        for j, (L, n, m) in enumerate(specs):
+            U, N = W.make_links(L, 0.3, 90 + j)
+            links = H.Links(L, dev(U), dev(N))
+            b = W.make_sources(L, n, 95 + j)
+            bd = dev(b)
+            x = torch.empty_like(bd)
+            keep.append((links, bd, x, U, N, b))
+            probs.append(H.Problem(H.geom(L), m, n, links.f64.data_ptr(),
+                                   links.packed(H.PREC_F32, naik).data_ptr() if mode == H.MODE_MIXED else None,
+                                   bd.data_ptr(), x.data_ptr()))
+            refs.append(H.solve(links, m, bd, mode=mode, naik=naik)[0])
+        p = H.hisq_default_params(mode=mode, naik=naik)
+        ws = H.empty_bytes(H.hisq_batched_workspace_bytes(probs, mode))
+        status, infos = H.hisq_cg_solve_batched(probs, p, ws)
+        assert status == H.HISQ_OK
+        for j, (L, n, m) in enumerate(specs):
+            links, bd, x, U, N, b = keep[j]
+            xh = host(x)
+            res = oracle.residual(L, U, N, m, b, xh)
+            say("batched", mode, naik, L, n, infos[j].iters[:n], res.max())
+            assert res.max() <= 1e-10
+            assert rel_l2_per_rhs(xh, host(refs[j])) <= 1e-7
+
+
+def test_headline_mixed_8rhs_true_residual():
+    """48^3 x 12, m = 0.01, eps = 0.2, 8 rhs, mixed precision with r14 Naik
+    links: the oracle's FP64 true residual of the returned x is <= 1e-10."""
+    H = gpu_lib()
+    L, m, n = (48, 48, 48, 12), 0.01, 8
+    U, N = W.make_links(L, 0.2, W.links_seed(3))
+    links = H.Links(L, dev(U), dev(N))
+    b = W.make_sources(L, n, W.sources_seed(3))
+    for nk in (H.NAIK_R14, H.NAIK_FULL):
+        x, status, info = H.solve(links, m, dev(b), mode=H.MODE_MIXED, naik=nk)
+        say("headline", nk, info["iters"], info["reliable_updates"], info["seconds"])
+        assert status == H.HISQ_OK
+        res = oracle.residual(L, U, N, m, b, host(x))
+        say("oracle true residual", res)
+        assert res.max() <= 1e-10

@@ -1,0 +1,156 @@
+"""GPU half-Dslash (Sec. 1, eqs. (3)-(4)) against the FP64 CPU oracle.
+
+FP64 within 1e-13 and FP32 (full or r14 Naik) within 1e-6 relative L2 per rhs,
+for n = 1..8, both output parities, every rhs-per-thread tile and work-group
+size, on lattices with wrap aliasing (L = 4: x+3 = x-1; L = 6: x+3 = x-3) and
+with ragged last tiles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_4439_amd import workload as W
+from tests.gpu_util import dev, gpu_lib, host, rel_l2_per_rhs, say
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [(4, 4, 4, 4), (6, 4, 6, 4), (8, 6, 4, 10), (16, 16, 16, 4)]
+_cache = {}
+
+
+def _links(H, L):
+    if L not in _cache:
+        U, N = W.make_links(L, 0.3, 7 + sum(L))
+        _cache[L] = (U, N, H.Links(L, dev(U), dev(N)))
+    return _cache[L]
+
+
+def _source(L, n, seed):
+    return W.make_sources(L, n, seed)
+
+
+def _tiles(n):
+    return [n // g for g in (1, 2, 4, 8) if n % g == 0]
+
+
+@pytest.fixture(autouse=True)
+def _reset_tuning():
+    yield
+    H = gpu_lib()
+    H.hisq_set_tuning(0)
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8])
+def test_dslash_f64_all_tiles(L, n):
+    H = gpu_lib()
+    U, N, links = _links(H, L)
+    for parity in (0, 1):
+        v = _source(L, n, 100 + n + parity)
+        want = oracle.dslash_eo(L, U, N, v, parity)
+        outs = []
+        for nr in _tiles(n):
+            for bs in (64, 256):
+                say("f64", L, n, parity, nr, bs)
+                H.hisq_set_tuning(1, nr, bs)
+                got = host(H.dslash(links, parity, dev(v), H.PREC_F64))
+                assert rel_l2_per_rhs(got, want) <= 1e-13, (nr, bs)
+                outs.append(got)
+        # the per-site arithmetic order does not depend on the tile: bitwise equal
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("L", LATTICES)
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 7, 8])
+@pytest.mark.parametrize("naik", ["full", "r14"])
+def test_dslash_f32_all_tiles(L, n, naik):
+    H = gpu_lib()
+    U, N, links = _links(H, L)
+    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_FULL
+    for parity in (0, 1):
+        v = _source(L, n, 200 + n + parity).astype(np.complex64)
+        want = oracle.dslash_eo(L, U, N, v.astype(np.complex128), parity)
+        for nr in _tiles(n):
+            for bs in (64, 128):
+                say("f32", naik, L, n, parity, nr, bs)
+                H.hisq_set_tuning(1, nr, bs)
+                got = host(H.dslash(links, parity, dev(v), H.PREC_F32, nk)).astype(np.complex128)
+                assert rel_l2_per_rhs(got, want) <= 1e-6, (nr, bs)
+
+
+@pytest.mark.parametrize("c", [1.0, -1.0 / 24.0])
+def test_dslash_free_field_closed_form(c):
+    """Unit links: plane waves are eigenvectors, lambda = 2i sum(sin p + c sin 3p)."""
+    H = gpu_lib()
+    L = (8, 4, 6, 4)
+    U, N = W.free_links(L, c)
+    links = H.Links(L, dev(U), dev(N))
+    for k in [(1, 0, 0, 0), (2, 1, 3, 1), (7, 3, 5, 2)]:
+        pw = W.plane_wave(L, k, [1.0, -0.5j, 0.25])
+        lam = 2j * sum(np.sin(2 * np.pi * k[mu] / L[mu]) + c * np.sin(6 * np.pi * k[mu] / L[mu])
+                       for mu in range(4))
+        ve, vo = W.to_half(pw, L, 0), W.to_half(pw, L, 1)
+        got = host(H.dslash(links, 1, dev(ve), H.PREC_F64))
+        assert np.linalg.norm(got - lam * vo) <= 1e-13 * np.linalg.norm(vo)
+
+
+def test_dslash_anti_hermitian_on_gpu():
+    H = gpu_lib()
+    L = (6, 4, 6, 4)
+    U, N, links = _links(H, L)
+    v = _source(L, 2, 301)
+    w = _source(L, 2, 302)
+    lhs = np.vdot(w, host(H.dslash(links, 0, dev(v), H.PREC_F64)))
+    rhs = -np.vdot(host(H.dslash(links, 1, dev(w), H.PREC_F64)), v)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_dslash_autotuned_and_bundle_independence():
+    H = gpu_lib()
+    L = (16, 16, 16, 4)
+    U, N, links = _links(H, L)
+    v = _source(L, 8, 401)
+    H.hisq_set_tuning(0)
+    got = host(H.dslash(links, 0, dev(v), H.PREC_F64))
+    for k in (0, 3, 7):
+        single = host(H.dslash(links, 0, dev(np.ascontiguousarray(v[:, :, k:k + 1])), H.PREC_F64))
+        assert np.array_equal(single[:, :, 0], got[:, :, k])
+
+
+def test_pack_rejects_non_unitary_naik():
+    H = gpu_lib()
+    L = (4, 4, 4, 4)
+    U, N = W.make_links(L, 0.3, 5)
+    N = N.copy()
+    N[2, 17] += 0.1 * np.eye(3) * 1j
+    buf = H.empty_bytes(H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_R14))
+    with pytest.raises(H.HisqError) as e:
+        H.hisq_pack_links(L, dev(U), dev(N), H.PREC_F32, H.NAIK_R14, buf)
+    assert e.value.code == H.HISQ_EPACK
+
+
+def test_dslash_headline_lattice_sampled_sites():
+    """48^3 x 12, n = 8, FP32 and r14, in the autotuned launch shape the solver
+    and the benchmark use: sampled output sites against the oracle, and the
+    whole output against the FP64 GPU Dslash of the same input."""
+    H = gpu_lib()
+    L = (48, 48, 48, 12)
+    U, N = W.make_links(L, 0.2, W.links_seed(3))
+    links = H.Links(L, dev(U), dev(N))
+    v = W.make_sources(L, 8, W.sources_seed(3))
+    v32 = v.astype(np.complex64)
+    rng = np.random.default_rng(9)
+    odd = np.flatnonzero(~W.even_mask(L))
+    sites = np.sort(rng.choice(odd, 2048, replace=False))
+    sites = np.concatenate([odd[:64], sites, odd[-64:]])
+    want = oracle.dslash_sites(L, U, N, v32.astype(np.complex128), 1, sites)
+    ref64 = H.dslash(links, 1, dev(v), H.PREC_F64)
+    assert rel_l2_per_rhs(host(ref64)[sites // 2], oracle.dslash_sites(L, U, N, v, 1, sites)) <= 1e-13
+    H.hisq_set_tuning(0)
+    for nk in (H.NAIK_FULL, H.NAIK_R14):
+        say("headline", nk)
+        got = H.dslash(links, 1, dev(v32), H.PREC_F32, nk)
+        g = host(got).astype(np.complex128)
+        assert rel_l2_per_rhs(g[sites // 2], want) <= 1e-6
+        assert rel_l2_per_rhs(g, host(ref64)) <= 1e-6

@@ -157,3 +157,16 @@ def test_bad_geometry_rejected():
     U, N = W.free_links((4, 4, 4, 4))
     with pytest.raises(ValueError):
         oracle.dslash_eo((5, 4, 4, 4), U, N, np.zeros((40, 3, 1)), 0)
+
+
+def test_sampled_sites_match_full_pass():
+    L = (6, 4, 4, 6)
+    U, N = W.make_links(L, 0.3, 141)
+    v = W.to_half(_rand_full(L, 3, 7), L, 1)
+    full = oracle.dslash_eo(L, U, N, v, 0)
+    even = np.flatnonzero(W.even_mask(L))
+    pick = even[[0, 5, 17, len(even) - 1]]
+    part = oracle.dslash_sites(L, U, N, v, 0, pick)
+    assert np.array_equal(part, full[pick // 2])
+    with pytest.raises(ValueError):
+        oracle.dslash_sites(L, U, N, v, 0, [1])  # site 1 is odd
