@@ -109,6 +109,15 @@ def main():
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / args.steps
 
+    # the same solve without per-kernel events, each poll block one hipGraph
+    graph_s = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        st, _ = step(profile=0)
+        torch.cuda.synchronize()
+        graph_s.append(time.perf_counter() - tg)
+
     # kernel-level figures from the HIP events recorded inside the timed steps
     nk = "r14" if naik == H.NAIK_R14 else "full"
     link_b = R.LINK_BYTES_F32[nk]
@@ -159,11 +168,12 @@ def main():
                     "pupdate": {"avg_ms": round(avg_ms[0], 5), "GBps": round(gbps_pu, 1),
                                 "launches": tot_n[0]},
                     "reliable_update": {"avg_ms": round(avg_ms[3], 4), "count": tot_n[3]}},
-        "cg": {"mixed_seconds": round(ms_per_step / 1e3, 4), "iters": iters,
+        "cg": {"mixed_seconds": round(ms_per_step / 1e3, 4),
+               "mixed_seconds_graph": round(min(graph_s), 4), "iters": iters,
                "reliable_updates": infos[-1]["reliable_updates"],
                "rel_true_res_max": max(infos[-1]["rel_true_res"]),
                "tile": {"rhs_per_thread": infos[-1]["rhs_per_thread"],
-                        "block": infos[-1]["block_size"]}},
+                        "block": infos[-1]["block_size"], "order": infos[-1]["tile_order"]}},
     }
 
     if not args.no_fp64_compare:

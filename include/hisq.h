@@ -109,6 +109,7 @@ typedef struct {
     int32_t total_iters;                 /* iterations of the bundle (max over rhs)     */
     int32_t block_size;                  /* tuned work-group size of the Dslash         */
     int32_t rhs_per_thread;              /* tuned rhs tile of the Dslash                */
+    int32_t tile_order;                  /* tuned work-group -> tile order (0, 1, 2)    */
     double seconds;                      /* host wall time of the solve                 */
     double kernel_ms[HISQ_K_COUNT];      /* profile = 1: summed event time per class    */
     int32_t kernel_launches[HISQ_K_COUNT];
@@ -208,13 +209,17 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
 
 /*
  * Autotuner control (process-wide).  mode 0: time the candidate tiles on first
- * use of a (lattice, nrhs, precision, Naik) key and cache the fastest (default);
- * mode 1: always use rhs_per_thread / block_size; mode 2: built-in default, no
- * timing.  rhs_per_thread must divide the bundle with a power-of-two quotient,
- * block_size in {64, 128, 256}; otherwise the forced tile is ignored for that
- * bundle.  Returns HISQ_EINVAL for an unknown mode or out-of-range values.
+ * use of a (lattice, nrhs, precision, Naik, kernel) key and cache the fastest
+ * (default); mode 1: always use rhs_per_thread / block_size / tile_order;
+ * mode 2: built-in default, no timing.  rhs_per_thread must divide the bundle
+ * with a power-of-two quotient (otherwise the forced tile is ignored for that
+ * bundle), block_size is 64, 128 or 256, tile_order is 0 (canonical site
+ * order), 1 (a contiguous slab of tiles per XCD) or 2 (per XCD, the time
+ * slices of one slice position back to back; falls back to 1 where tiles
+ * would straddle a time slice).  The order only changes cache locality, never
+ * results.  Returns HISQ_EINVAL for an unknown mode or out-of-range values.
  */
-int hisq_set_tuning(int mode, int rhs_per_thread, int block_size);
+int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hisq_last_error(void);

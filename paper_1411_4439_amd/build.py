@@ -47,22 +47,29 @@ def _compile(job):
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 and link libhisq.so; returns its path."""
-    os.makedirs(BUILD, exist_ok=True)
-    work = _jobs()
+def build(jobs: int | None = None, verbose: bool = False, defines=(), out: str | None = None,
+          build_dir: str | None = None) -> str:
+    """Compile every HIP source for gfx950 and link libhisq.so; returns its path.
+
+    `defines` adds -D flags (tuning variants), `out` / `build_dir` redirect the
+    library and its objects."""
+    bdir = build_dir or BUILD
+    os.makedirs(bdir, exist_ok=True)
+    work = [(src, os.path.join(bdir, os.path.basename(obj)), list(d) + ["-D" + x for x in defines])
+            for src, obj, d in _jobs()]
     n = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(max_workers=n) as ex:
         objs = list(ex.map(_compile, work))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    lib = out or LIB
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -146,12 +146,12 @@ hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<f
 
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStream_t s)
 {
-    return launch_pupdate_f64(n, t, a, s);
+    return pupdate_flat_ok(n) ? launch_pupdate_flat_f64(n, a, s) : launch_pupdate_f64(n, t, a, s);
 }
 
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<float>& a, hipStream_t s)
 {
-    return launch_pupdate_f32(n, t, a, s);
+    return pupdate_flat_ok(n) ? launch_pupdate_flat_f32(n, a, s) : launch_pupdate_f32(n, t, a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -160,7 +160,14 @@ hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<float>& a, hipStre
 std::mutex g_tune_mu;
 std::map<std::string, Tile> g_tune_cache;
 int g_tune_mode = 0;
-int g_force_nr = 0, g_force_bs = 0;
+int g_force_nr = 0, g_force_bs = 0, g_force_order = 1;
+
+// Tile order 2 needs tiles that never straddle a time slice.
+bool t_order_ok(const Lat& lat, int G, int bs)
+{
+    const long slice_threads = (long)lat.Vh / lat.L[3] * G;
+    return slice_threads % bs == 0;
+}
 
 Tile default_tile(int n, int prec)
 {
@@ -190,15 +197,17 @@ template <typename T>
 int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& probe, hipStream_t s,
              Tile* out, int epi = EPI_PLAIN)
 {
-    int mode, fnr, fbs;
+    int mode, fnr, fbs, ford;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         mode = g_tune_mode;
         fnr = g_force_nr;
         fbs = g_force_bs;
+        ford = g_force_order;
     }
     if (mode == 1 && valid_nr(n, fnr)) {
-        *out = Tile{fnr, fbs, 1};
+        if (ford == 2 && !t_order_ok(lat, n / fnr, fbs)) ford = 1;
+        *out = Tile{fnr, fbs, ford};
         return HISQ_OK;
     }
     if (mode != 0) {
@@ -224,8 +233,9 @@ int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& pro
         if (n % G != 0) continue;
         const int nr = n / G;
         for (int bi = 0; bi < 3; ++bi)
-            for (int remap = 0; remap < 2; ++remap) {
+            for (int remap = 0; remap < 3; ++remap) {
                 const Tile c{nr, bss[bi], remap};
+                if (remap == 2 && !t_order_ok(lat, G, bss[bi])) continue;
                 if (launch_ds(epi, n, r14, c, probe, s) != hipSuccess) continue;
                 HIP_TRY(hipEventRecord(e0, s));
                 for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, r14, c, probe, s));
@@ -573,7 +583,13 @@ int Engine::setup(CgState* host)
         // b_k = 0: the solution is exactly 0, whatever the start vector
         for (Prob& q : P) HIP_TRY(launch_zero_sel(q.x, q.ncplx(), q.n, q.w.st, s));
         for (size_t j = 0; j < P.size(); ++j)
-            for (int k = 0; k < P[j].n; ++k) host[j].sel[k] = 0;
+            for (int k = 0; k < P[j].n; ++k) {
+                host[j].sel[k] = 0;
+                if (P[j].bb[k] == 0.0) {
+                    P[j].fin[k] = true;
+                    host[j].active[k] = 0;
+                }
+            }
         if ((rc = write_states(host))) return rc;
     }
     return HISQ_OK;
@@ -698,6 +714,7 @@ int Engine::finish(CgState* host, hisq_info* infos, double seconds)
             const Tile& t = mixed ? q.t32 : q.t64;
             info->block_size = P.size() == 1 ? t.bs : batch_bs;
             info->rhs_per_thread = t.nr;
+            info->tile_order = P.size() == 1 ? t.remap : 0;
         }
         int maxit = 0;
         for (int k = 0; k < q.n; ++k) {
@@ -1142,7 +1159,7 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
     return E.run(infos);
 }
 
-int hisq_set_tuning(int mode, int rhs_per_thread, int block_size)
+int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order)
 {
     if (mode < 0 || mode > 2) return fail(HISQ_EINVAL, "unknown tuning mode %d", mode);
     if (mode == 1) {
@@ -1150,11 +1167,13 @@ int hisq_set_tuning(int mode, int rhs_per_thread, int block_size)
             return fail(HISQ_EINVAL, "rhs_per_thread must be in 1..8");
         if (block_size != 64 && block_size != 128 && block_size != 256)
             return fail(HISQ_EINVAL, "block_size must be 64, 128 or 256");
+        if (tile_order < 0 || tile_order > 2) return fail(HISQ_EINVAL, "tile_order must be 0, 1 or 2");
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_mode = mode;
     g_force_nr = rhs_per_thread;
     g_force_bs = block_size;
+    g_force_order = mode == 1 ? tile_order : 1;
     return HISQ_OK;
 }
 

@@ -48,14 +48,19 @@ __device__ __forceinline__ C cconj(C a)
     return C{a.x, -a.y};
 }
 
+// Fused multiply-add in the storage precision (the plain __builtin_fma is the
+// double-precision builtin and would promote FP32 operands).
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // acc += m * v in four fused multiply-adds
 template <typename C>
 __device__ __forceinline__ void cfma(C& acc, C m, C v)
 {
-    acc.x = __builtin_fma(m.x, v.x, acc.x);
-    acc.x = __builtin_fma(-m.y, v.y, acc.x);
-    acc.y = __builtin_fma(m.x, v.y, acc.y);
-    acc.y = __builtin_fma(m.y, v.x, acc.y);
+    acc.x = fmadd(m.x, v.x, acc.x);
+    acc.x = fmadd(-m.y, v.y, acc.x);
+    acc.y = fmadd(m.x, v.y, acc.y);
+    acc.y = fmadd(m.y, v.x, acc.y);
 }
 
 __device__ __forceinline__ int wrap_delta(int c, int h, int L)
@@ -73,35 +78,31 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-// Registers holding one slot's operands: the matrix and the neighbour's
-// colour vectors of this thread's rhs tile.
-template <typename T, int NR>
-struct SlotRegs {
-    cplx<T> m[9];
-    cplx<T> v[3][NR];
-};
-
-template <typename T, int NRHS, int NR, bool R14, int S>
-__device__ __forceinline__ void load_slot(const cplx<T>* __restrict__ lk,
-                                          const cplx<T>* __restrict__ in, int Vh, int i,
-                                          int nbr, int g, SlotRegs<T, NR>& o)
+template <typename T, bool R14, int S>
+__device__ __forceinline__ void load_link(const cplx<T>* __restrict__ lk, int Vh, int i,
+                                          cplx<T> (&m)[9])
 {
-    using C = cplx<T>;
-    const C* lp = lk + link_slot_elem(S, R14) * Vh + i;
+    const cplx<T>* lp = lk + link_slot_elem(S, R14) * Vh + i;
     constexpr int ne = (R14 && S >= 8) ? 7 : 9;
 #pragma unroll
-    for (int e = 0; e < ne; ++e) o.m[e] = __builtin_nontemporal_load(lp + e * Vh);
-    const C* vp = in + (nbr * 3) * NRHS + g * NR;
+    for (int e = 0; e < ne; ++e) m[e] = __builtin_nontemporal_load(lp + e * Vh);
+}
+
+template <typename T, int NRHS, int NR>
+__device__ __forceinline__ void load_vec(const cplx<T>* __restrict__ in, int nbr, int g,
+                                         cplx<T> (&v)[3][NR])
+{
+    const cplx<T>* vp = in + (nbr * 3) * NRHS + g * NR;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + b * NRHS, o.v[b]);
+    for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + b * NRHS, v[b]);
 }
 
 template <typename T, int NR, bool R14, int S>
-__device__ __forceinline__ void apply_slot(SlotRegs<T, NR>& o, cplx<T> (&acc)[3][NR])
+__device__ __forceinline__ void apply_slot(cplx<T> (&m)[9], const cplx<T> (&v)[3][NR],
+                                           cplx<T> (&acc)[3][NR])
 {
     if constexpr (R14 && S >= 8) {
         // row 2 = c * conj(row0 x row1); c was loaded into m[6]
-        auto* m = o.m;
         const cplx<T> cc = m[6];
         m[6] = cmul(cc, cconj(cmul(m[1], m[5]) - cmul(m[2], m[4])));
         m[7] = cmul(cc, cconj(cmul(m[2], m[3]) - cmul(m[0], m[5])));
@@ -112,14 +113,52 @@ __device__ __forceinline__ void apply_slot(SlotRegs<T, NR>& o, cplx<T> (&acc)[3]
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int k = 0; k < NR; ++k) cfma(acc[a][k], o.m[3 * a + b], o.v[b][k]);
+            for (int k = 0; k < NR; ++k) cfma(acc[a][k], m[3 * a + b], v[b][k]);
+}
+
+// Site coordinates and the neighbour index of slot S = 4*hop + mu, hop
+// (+1, -1, +3, -3), in the other parity's index space.
+struct SiteCoord {
+    int i, row, x, c[4];
+};
+
+__device__ __forceinline__ SiteCoord site_coord(const Lat& lat, int P, int i)
+{
+    SiteCoord sc;
+    int r = i / lat.Lh0;
+    const int xh = i - r * lat.Lh0;
+    sc.c[1] = r % lat.L[1];
+    r /= lat.L[1];
+    sc.c[2] = r % lat.L[2];
+    sc.c[3] = r / lat.L[2];
+    sc.x = 2 * xh + ((P + sc.c[1] + sc.c[2] + sc.c[3]) & 1);
+    sc.c[0] = sc.x;
+    sc.row = i - xh;
+    sc.i = i;
+    return sc;
+}
+
+template <int S>
+__device__ __forceinline__ int neighbour(const Lat& lat, const SiteCoord& sc)
+{
+    constexpr int mu = S & 3;
+    constexpr int hh = S >> 2;
+    constexpr int h = hh == 0 ? 1 : hh == 1 ? -1 : hh == 2 ? 3 : -3;
+    if constexpr (mu == 0) {
+        const int xp = sc.x + wrap_delta(sc.x, h, lat.L[0]);
+        return sc.row + (xp >> 1);
+    } else {
+        const int stride = mu == 1 ? lat.sy : mu == 2 ? lat.sz : lat.st;
+        return sc.i + wrap_delta(sc.c[mu], h, lat.L[mu]) * stride;
+    }
 }
 
 // acc[c][k] = (D in)_{i}, colour c, rhs g*NR + k, output parity P.
 // Slot s = 4*hop + mu applies matrix s of the parity block to the neighbour
 // reached by hop (+1, -1, +3, -3) in direction mu.  The 16 slots run as a
-// two-stage pipeline: while slot s is multiplied, the matrix and neighbour
-// vectors of slot s+1 are in flight in the other register buffer.  The
+// software pipeline: while slot s is multiplied, the neighbour vectors of slot
+// s+1 and the matrices of slots s+1 and s+2 are in flight (links stream from
+// HBM and see the longest latency; neighbour vectors mostly hit L2).  The
 // scheduling barriers keep the compiler from hoisting further loads, which
 // would otherwise exhaust the register file.
 template <typename T, int NRHS, int NR, bool R14>
@@ -130,40 +169,29 @@ __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
 {
     using C = cplx<T>;
     const int Vh = lat.Vh;
-    int r = i / lat.Lh0;
-    const int xh = i - r * lat.Lh0;
-    const int y = r % lat.L[1];
-    r /= lat.L[1];
-    const int z = r % lat.L[2];
-    const int t = r / lat.L[2];
-    const int x = 2 * xh + ((P + y + z + t) & 1);
-    const int row = i - xh;
-
-    int nb[16];
-    const int hops[4] = {1, -1, 3, -3};
-#pragma unroll
-    for (int hh = 0; hh < 4; ++hh) {
-        const int h = hops[hh];
-        const int xp = x + wrap_delta(x, h, lat.L[0]);
-        nb[4 * hh + 0] = row + (xp >> 1);
-        nb[4 * hh + 1] = i + wrap_delta(y, h, lat.L[1]) * lat.sy;
-        nb[4 * hh + 2] = i + wrap_delta(z, h, lat.L[2]) * lat.sz;
-        nb[4 * hh + 3] = i + wrap_delta(t, h, lat.L[3]) * lat.st;
-    }
-
+    const SiteCoord sc = site_coord(lat, P, i);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[c][k] = C{0, 0};
 
-    SlotRegs<T, NR> buf[2];
-    load_slot<T, NRHS, NR, R14, 0>(lk, in, Vh, i, nb[0], g, buf[0]);
+    // link lookahead: two slots in FP32; one in FP64, whose 36-register
+    // matrices would otherwise cost a wave of occupancy
+#ifndef HISQ_FP32_LINK_LOOKAHEAD
+#define HISQ_FP32_LINK_LOOKAHEAD 1
+#endif
+    constexpr int LD = sizeof(T) == 4 ? HISQ_FP32_LINK_LOOKAHEAD : 1;
+    C m[LD + 1][9];
+    C v[2][3][NR];
+    load_link<T, R14, 0>(lk, Vh, i, m[0]);
+    if constexpr (LD == 2) load_link<T, R14, 1>(lk, Vh, i, m[1]);
+    load_vec<T, NRHS, NR>(in, neighbour<0>(lat, sc), g, v[0]);
     static_for<0, 16>([&](auto S) {
         constexpr int s = decltype(S)::value;
-        if constexpr (s + 1 < 16)
-            load_slot<T, NRHS, NR, R14, s + 1>(lk, in, Vh, i, nb[s + 1], g, buf[(s + 1) & 1]);
+        if constexpr (s + LD < 16) load_link<T, R14, s + LD>(lk, Vh, i, m[(s + LD) % (LD + 1)]);
+        if constexpr (s + 1 < 16) load_vec<T, NRHS, NR>(in, neighbour<s + 1>(lat, sc), g, v[(s + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
-        apply_slot<T, NR, R14, s>(buf[s & 1], acc);
+        apply_slot<T, NR, R14, s>(m[s % (LD + 1)], v[s & 1], acc);
         __builtin_amdgcn_sched_barrier(0);
     });
 }
@@ -183,6 +211,7 @@ __device__ __forceinline__ void pin_acc(C (&acc)[3][NR])
 template <int EPI>
 __device__ __forceinline__ void finish(CgState* st, int k, double tot, double m4)
 {
+    if (st->frozen) return;
     if constexpr (EPI == EPI_NORM) {
         // alpha = rr / <p, A p>, with <p, A p> = 4m^2 |p|^2 + |D_oe p|^2 (D_eo^dag = -D_oe)
         st->tt[k] = tot;
@@ -321,10 +350,16 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
     }
 }
 
+#ifdef HISQ_WAVES_PER_EU
+#define HISQ_KATTR __attribute__((amdgpu_waves_per_eu(HISQ_WAVES_PER_EU)))
+#else
+#define HISQ_KATTR
+#endif
+
 template <typename T, int NRHS, int NR, bool R14, int EPI>
-__global__ __launch_bounds__(kMaxBlock) void k_dslash(const DslashArgs<T> a)
+__global__ __launch_bounds__(kMaxBlock) HISQ_KATTR void k_dslash(const DslashArgs<T> a)
 {
-    dslash_tile<T, NRHS, NR, R14, EPI>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap), gridDim.x,
+    dslash_tile<T, NRHS, NR, R14, EPI>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat.L[3]), gridDim.x,
                                        blockIdx.x);
 }
 

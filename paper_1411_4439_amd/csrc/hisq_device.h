@@ -6,17 +6,26 @@
 
 namespace hisq {
 
-// Work-group -> tile map.  Work-groups are dealt to the 8 XCDs of the chip
-// round-robin (work-group b starts on XCD b mod 8).  With `remap` set, the
-// tiles are split into 8 contiguous ranges and XCD j walks range j in order, so
-// each XCD's L2 sees a contiguous slab of the lattice and the stencil's
-// neighbours are mostly resident in the same L2.  A bijection on [0, gridDim).
-__device__ inline int tile_of_block(int b, int nb, int remap)
+// Work-group -> tile map (a bijection on [0, nb); correctness never depends on
+// it, only cache locality does).  Work-groups are dealt to the 8 XCDs of the
+// chip round-robin (work-group b starts on XCD b mod 8).
+//   order 0: tile = b.
+//   order 1: the tiles are split into 8 contiguous ranges and XCD j walks range
+//            j in order, so each XCD's L2 sees a contiguous slab of the lattice.
+//   order 2: as 1, but the walk visits all Lt time slices of one position of the
+//            slice before moving on (t fastest).  An input site is read by the
+//            outputs at t+-1 and t+-3; in canonical order those run a whole time
+//            slice apart and the site is fetched again for each, in this order
+//            they run back to back and hit L2.  Needs nb = Lt * (tiles per slice).
+__device__ inline int tile_of_block(int b, int nb, int order, int Lt)
 {
-    if (!remap || nb < 8) return b;
+    if (order == 0 || nb < 8) return b;
     const int j = b & 7, m = b >> 3;
     const int q = nb >> 3, rem = nb & 7;
-    return j * q + (j < rem ? j : rem) + m;
+    const int c = j * q + (j < rem ? j : rem) + m;  // XCD-contiguous position
+    if (order == 1) return c;
+    const int per_slice = nb / Lt;
+    return (c % Lt) * per_slice + c / Lt;
 }
 
 __device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }

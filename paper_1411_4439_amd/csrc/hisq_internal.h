@@ -107,7 +107,8 @@ struct CgState {
     int32_t iters[kMaxRhs];
     int32_t sel[kMaxRhs];    // rhs selected for the next true-residual pass
     int32_t maxiter;
-    int32_t pad[7];
+    int32_t frozen;          // 1 while the autotuner times kernels: finishers write nothing
+    int32_t pad[6];
 };
 
 enum Epi {
@@ -201,6 +202,10 @@ hipError_t launch_pupdate_batched_f32(const BatchTable<float>* tab, int total_bl
                                       hipStream_t s);
 // rhs-per-thread tiles the batched kernels are built for
 inline bool batched_nr_ok(int n, int nr) { return nr == n || (n % 2 == 0 && nr == n / 2); }
+// Streaming p-update for bundles of 1, 2, 4 or 8 rhs (any tile).
+inline bool pupdate_flat_ok(int n) { return n == 1 || n == 2 || n == 4 || n == 8; }
+hipError_t launch_pupdate_flat_f64(int nrhs, const PupdateArgs<double>& a, hipStream_t s);
+hipError_t launch_pupdate_flat_f32(int nrhs, const PupdateArgs<float>& a, hipStream_t s);
 hipError_t launch_pupdate_f64(int nrhs, const Tile& t, const PupdateArgs<double>& a,
                               hipStream_t s);
 hipError_t launch_pupdate_f32(int nrhs, const Tile& t, const PupdateArgs<float>& a,

@@ -12,7 +12,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhisq.so")
+# HISQ_LIBRARY_PATH selects another build of the same library (e.g. an
+# experimental tuning variant); the default is the in-tree libhisq.so.
+LIB_PATH = os.environ.get("HISQ_LIBRARY_PATH") or os.path.join(_HERE, "libhisq.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libhisq.so is not built (run __graft_entry__.build() or "
@@ -46,7 +48,8 @@ class Info(ctypes.Structure):
                 ("rel_true_res", ctypes.c_double * 8), ("rel_iter_res", ctypes.c_double * 8),
                 ("reliable_updates", ctypes.c_int32), ("polls", ctypes.c_int32),
                 ("total_iters", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("rhs_per_thread", ctypes.c_int32), ("seconds", ctypes.c_double),
+                ("rhs_per_thread", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("seconds", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int32 * 4)]
 
     def to_dict(self, nrhs):
@@ -56,7 +59,8 @@ class Info(ctypes.Structure):
             "rel_iter_res": list(self.rel_iter_res[:nrhs]),
             "reliable_updates": self.reliable_updates, "polls": self.polls,
             "total_iters": self.total_iters, "block_size": self.block_size,
-            "rhs_per_thread": self.rhs_per_thread, "seconds": self.seconds,
+            "rhs_per_thread": self.rhs_per_thread, "tile_order": self.tile_order,
+            "seconds": self.seconds,
             "kernel_ms": list(self.kernel_ms), "kernel_launches": list(self.kernel_launches),
         }
 
@@ -87,7 +91,7 @@ _sig = {
     "hisq_cg_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem),
                                              ctypes.POINTER(Params), _P, ctypes.c_size_t,
                                              ctypes.POINTER(Info), _P]),
-    "hisq_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "hisq_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "hisq_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -211,8 +215,9 @@ def hisq_cg_solve_batched(problems, params, ws, stream=None):
     return _check(rc, "hisq_cg_solve_batched"), list(infos)
 
 
-def hisq_set_tuning(mode, rhs_per_thread=0, block_size=0):
-    return _check(_lib.hisq_set_tuning(mode, rhs_per_thread, block_size), "hisq_set_tuning")
+def hisq_set_tuning(mode, rhs_per_thread=0, block_size=0, tile_order=1):
+    return _check(_lib.hisq_set_tuning(mode, rhs_per_thread, block_size, tile_order),
+                  "hisq_set_tuning")
 
 
 def hisq_last_error():

@@ -50,13 +50,14 @@ def test_dslash_f64_all_tiles(L, n):
         want = oracle.dslash_eo(L, U, N, v, parity)
         outs = []
         for nr in _tiles(n):
-            for bs in (64, 256):
-                say("f64", L, n, parity, nr, bs)
-                H.hisq_set_tuning(1, nr, bs)
+            for bs, order in ((64, 0), (64, 2), (256, 1), (256, 2)):
+                say("f64", L, n, parity, nr, bs, order)
+                H.hisq_set_tuning(1, nr, bs, order)
                 got = host(H.dslash(links, parity, dev(v), H.PREC_F64))
-                assert rel_l2_per_rhs(got, want) <= 1e-13, (nr, bs)
+                assert rel_l2_per_rhs(got, want) <= 1e-13, (nr, bs, order)
                 outs.append(got)
-        # the per-site arithmetic order does not depend on the tile: bitwise equal
+        # the per-site arithmetic order depends on neither the tile nor the tile
+        # order: bitwise equal
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
 
@@ -72,11 +73,11 @@ def test_dslash_f32_all_tiles(L, n, naik):
         v = _source(L, n, 200 + n + parity).astype(np.complex64)
         want = oracle.dslash_eo(L, U, N, v.astype(np.complex128), parity)
         for nr in _tiles(n):
-            for bs in (64, 128):
-                say("f32", naik, L, n, parity, nr, bs)
-                H.hisq_set_tuning(1, nr, bs)
+            for bs, order in ((64, 2), (128, 1)):
+                say("f32", naik, L, n, parity, nr, bs, order)
+                H.hisq_set_tuning(1, nr, bs, order)
                 got = host(H.dslash(links, parity, dev(v), H.PREC_F32, nk)).astype(np.complex128)
-                assert rel_l2_per_rhs(got, want) <= 1e-6, (nr, bs)
+                assert rel_l2_per_rhs(got, want) <= 1e-6, (nr, bs, order)
 
 
 @pytest.mark.parametrize("c", [1.0, -1.0 / 24.0])
