@@ -200,19 +200,29 @@ def main():
         sweep = {}
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        for prec, nk2, tag in ((H.PREC_F64, H.NAIK_FULL, "f64"), (H.PREC_F32, H.NAIK_FULL, "f32"),
-                               (H.PREC_F32, H.NAIK_R14, "f32_r14")):
-            for nn in (1, 2, 4, 8):
+        # the solver's colour-major field order, plus the caller's site-major
+        # order at the largest bundle for comparison
+        cases = [(prec, nk2, tag, nn, H.LAYOUT_COLOUR)
+                 for prec, nk2, tag in ((H.PREC_F64, H.NAIK_FULL, "f64"),
+                                        (H.PREC_F32, H.NAIK_FULL, "f32"),
+                                        (H.PREC_F32, H.NAIK_R14, "f32_r14"))
+                 for nn in (1, 2, 4, 8)]
+        cases.append((H.PREC_F32, H.NAIK_R14, "f32_r14_sitemajor", n, H.LAYOUT_SITE))
+        for prec, nk2, tag, nn, lay in cases:
+            if True:
                 dt = torch.complex128 if prec == H.PREC_F64 else torch.complex64
-                vin = bd[:, :, :nn].contiguous().to(dt)
+                vin = bd[:, :, :nn].to(dt)
+                if lay == H.LAYOUT_COLOUR:
+                    vin = vin.permute(1, 0, 2)
+                vin = vin.contiguous()
                 vout = torch.empty_like(vin)
                 packed = links.packed(prec, nk2)
                 for _ in range(3):
-                    H.hisq_dslash(L, 1, nn, prec, nk2, packed, vin, vout)
+                    H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
                 reps = 20
                 ev0.record(stream)
                 for _ in range(reps):
-                    H.hisq_dslash(L, 1, nn, prec, nk2, packed, vin, vout)
+                    H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
                 ev1.record(stream)
                 ev1.synchronize()
                 ms = ev0.elapsed_time(ev1) / reps

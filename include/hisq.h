@@ -30,8 +30,10 @@
  *            interleaved (re, im), row-major 3x3.  Staggered phases and boundary
  *            signs must already be folded in.  Packed links are opaque.
  * Fields     half-lattice, one parity: [Vh][3][n] complex, rhs innermost; the row
- *            of site s is s/2.  Complex128 at the solver boundary; in the storage
- *            precision (complex64 or complex128) for hisq_dslash.
+ *            of site s is s/2 ("site-major").  Complex128 at the solver
+ *            boundary; in the storage precision (complex64 or complex128) for
+ *            hisq_dslash, which also accepts the colour-major order [3][Vh][n]
+ *            that the solvers iterate on internally.
  * Memory     every data pointer is a DEVICE pointer owned by the caller, except
  *            hisq_info / hisq_params / hisq_problem structs, which are host memory.
  *            The library allocates no device memory; solvers take a workspace
@@ -72,6 +74,8 @@ extern "C" {
 enum hisq_prec { HISQ_PREC_F64 = 0, HISQ_PREC_F32 = 1 };
 enum hisq_naik { HISQ_NAIK_FULL = 0, HISQ_NAIK_R14 = 1 };
 enum hisq_mode { HISQ_MODE_FP64 = 0, HISQ_MODE_MIXED = 1 };
+/* field order: [Vh][3][n] (site-major, the default) or [3][Vh][n] */
+enum hisq_layout { HISQ_LAYOUT_SITE = 0, HISQ_LAYOUT_COLOUR = 1 };
 
 typedef struct {
     int32_t L[4];
@@ -162,10 +166,13 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
 /*
  * out = D_{out_parity, 1-out_parity} in  (Sec. 1 eqs. (3)-(4)): the HISQ Dslash
  * from the fields of parity 1-out_parity to those of parity out_parity, for
- * nrhs independent rhs sharing every link load.  `in`, `out`: [Vh][3][nrhs]
- * complex in the storage precision `prec` of `packed`.  Asynchronous.
+ * nrhs independent rhs sharing every link load.  `in`, `out`: complex in the
+ * storage precision `prec` of `packed`, in the order `layout` (HISQ_LAYOUT_*):
+ * [Vh][3][nrhs] or [3][Vh][nrhs].  The colour-major order lets the 64 lanes of
+ * a wavefront read one contiguous stretch per colour; the solvers use it.
+ * Asynchronous.
  */
-int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik,
+int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik, int layout,
                 const void* packed, const void* in, void* out, void* stream);
 
 /*
@@ -173,7 +180,8 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
  * links64: packed FP64/FULL links (always needed: FP64 mode iterates on them,
  * MIXED mode uses them for the true residual).  links32: packed FP32 links
  * with Naik storage params->naik (MIXED only; may be NULL in FP64 mode).
- * b_e, x_e: [Vh][3][nrhs] complex128 device buffers.  Ends when every rhs has
+ * b_e, x_e: [Vh][3][nrhs] complex128 device buffers (copied into the
+ * colour-major working order inside the workspace).  Ends when every rhs has
  * ||b_k - A x_k|| <= tol ||b_k|| recomputed in FP64 from x, or failed.  Returns
  * HISQ_OK, or the worst per-rhs status (NOT_CONVERGED < BREAKDOWN), or < 0.
  */

@@ -84,6 +84,8 @@ struct Ws {
     f2* p32 = nullptr;
     f2* t32 = nullptr;
     f2* x32 = nullptr;
+    d2* xc = nullptr;  // colour-major copies of x and b (the solver's layout)
+    d2* bc = nullptr;
     d2* y = nullptr;  // backward: adjoint solution, D_oe x, D_oe y
     d2* tx = nullptr;
     d2* sy = nullptr;
@@ -106,6 +108,8 @@ size_t ws_layout(const Lat& lat, int n, int mode, bool backward, char* base, Ws*
     w->cnt = (uint32_t*)take(w->cnt_bytes);
     w->r64 = (d2*)take(f64);
     w->t64 = (d2*)take(f64);
+    w->xc = (d2*)take(f64);
+    w->bc = (d2*)take(f64);
     if (mode == HISQ_MODE_FP64) {
         w->p64 = (d2*)take(f64);
     } else {
@@ -131,17 +135,19 @@ const cplx<T>* link_block(const void* packed, int Vh, bool r14, int parity)
     return reinterpret_cast<const cplx<T>*>(b) + (size_t)parity * link_block_elems(Vh, r14);
 }
 
+// cm: colour-major fields (every solver launch); false only for the plain
+// Dslash on canonical site-major fields.
 hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<double>& a,
-                     hipStream_t s)
+                     hipStream_t s, bool cm = true)
 {
     (void)r14;
-    return launch_dslash_f64(epi, n, t, a, s);
+    return launch_dslash_f64(epi, n, t, a, s, cm);
 }
 
 hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<float>& a,
-                     hipStream_t s)
+                     hipStream_t s, bool cm = true)
 {
-    return r14 ? launch_dslash_f32r14(epi, n, t, a, s) : launch_dslash_f32(epi, n, t, a, s);
+    return r14 ? launch_dslash_f32r14(epi, n, t, a, s, cm) : launch_dslash_f32(epi, n, t, a, s, cm);
 }
 
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStream_t s)
@@ -182,11 +188,11 @@ Tile default_tile(int n, int prec)
     return t;
 }
 
-std::string tune_key(const Lat& lat, int n, int prec, int naik, int epi)
+std::string tune_key(const Lat& lat, int n, int prec, int naik, int epi, bool cm)
 {
     char buf[128];
-    snprintf(buf, sizeof(buf), "%dx%dx%dx%d/n%d/p%d/k%d/e%d", lat.L[0], lat.L[1], lat.L[2],
-             lat.L[3], n, prec, naik, epi);
+    snprintf(buf, sizeof(buf), "%dx%dx%dx%d/n%d/p%d/k%d/e%d/c%d", lat.L[0], lat.L[1], lat.L[2],
+             lat.L[3], n, prec, naik, epi, cm ? 1 : 0);
     return buf;
 }
 
@@ -195,7 +201,7 @@ std::string tune_key(const Lat& lat, int n, int prec, int naik, int epi)
 // tile (probe.state/red/cnt must then be valid, counters zero, rhs active).
 template <typename T>
 int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& probe, hipStream_t s,
-             Tile* out, int epi = EPI_PLAIN)
+             Tile* out, int epi = EPI_PLAIN, bool cm = true)
 {
     int mode, fnr, fbs, ford;
     {
@@ -214,7 +220,7 @@ int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& pro
         *out = default_tile(n, prec);
         return HISQ_OK;
     }
-    const std::string key = tune_key(lat, n, prec, r14 ? 1 : 0, epi);
+    const std::string key = tune_key(lat, n, prec, r14 ? 1 : 0, epi, cm);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -236,9 +242,9 @@ int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& pro
             for (int remap = 0; remap < 3; ++remap) {
                 const Tile c{nr, bss[bi], remap};
                 if (remap == 2 && !t_order_ok(lat, G, bss[bi])) continue;
-                if (launch_ds(epi, n, r14, c, probe, s) != hipSuccess) continue;
+                if (launch_ds(epi, n, r14, c, probe, s, cm) != hipSuccess) continue;
                 HIP_TRY(hipEventRecord(e0, s));
-                for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, r14, c, probe, s));
+                for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, r14, c, probe, s, cm));
                 HIP_TRY(hipEventRecord(e1, s));
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0;
@@ -306,7 +312,9 @@ struct Prob {
     double mass = 0, m4 = 0;
     const void* links64 = nullptr;
     const void* links32 = nullptr;
-    const d2* b = nullptr;
+    const d2* ub = nullptr;  // caller's b and x, site-major [Vh][3][n]
+    d2* ux = nullptr;
+    const d2* b = nullptr;  // colour-major working copies [3][Vh][n]
     d2* x = nullptr;
     Ws w;
     Tile t64{}, t32{};
@@ -544,7 +552,11 @@ int Engine::setup(CgState* host)
         const size_t nc = q.ncplx();
         HIP_TRY(launch_zero(q.w.cnt, q.w.cnt_bytes, s));
         HIP_TRY(launch_state_reset(q.w.st, q.n, 0, s));
-        if (!prm.use_x0) HIP_TRY(launch_zero(q.x, nc * sizeof(d2), s));
+        HIP_TRY(launch_layout(q.ub, q.w.bc, q.lat.Vh, q.n, true, s));
+        if (prm.use_x0)
+            HIP_TRY(launch_layout(q.ux, q.w.xc, q.lat.Vh, q.n, true, s));
+        else
+            HIP_TRY(launch_zero(q.x, nc * sizeof(d2), s));
         HIP_TRY(launch_norm2_f64(q.b, q.lat.Vh, q.n, q.w.st->aux, q.w.red, q.w.cnt, s));
         if ((rc = true_residual(q))) return rc;
         if (mixed) {
@@ -703,6 +715,7 @@ int Engine::finish(CgState* host, hisq_info* infos, double seconds)
     for (Prob& q : P) {
         if (mixed) HIP_TRY(launch_accum_sel(q.x, q.w.x32, q.ncplx(), q.n, q.w.st, s));
         if ((rc = true_residual(q))) return rc;
+        HIP_TRY(launch_layout(q.x, q.ux, q.lat.Vh, q.n, false, s));
     }
     if ((rc = read_states(host))) return rc;
     int worst = HISQ_OK;
@@ -868,8 +881,10 @@ int solve_impl(double mass, int nrhs, const hisq_params* p, const void* links64,
     q.m4 = 4.0 * mass * mass;
     q.links64 = links64;
     q.links32 = links32;
-    q.b = reinterpret_cast<const d2*>(b_e);
-    q.x = reinterpret_cast<d2*>(x_e);
+    q.ub = reinterpret_cast<const d2*>(b_e);
+    q.ux = reinterpret_cast<d2*>(x_e);
+    q.b = w.bc;
+    q.x = w.xc;
     q.w = w;
     E.states = w.st;
     E.P.push_back(q);
@@ -1002,7 +1017,7 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
     return HISQ_OK;
 }
 
-int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik,
+int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik, int layout,
                 const void* packed, const void* in, void* out, void* stream)
 {
     (void)hipGetLastError();  // drop a stale error left by an earlier failed call
@@ -1016,8 +1031,11 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
     if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return fail(HISQ_EINVAL, "bad naik %d", naik);
     if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32)
         return fail(HISQ_EINVAL, "r14 Naik storage is FP32 only");
+    if (layout != HISQ_LAYOUT_SITE && layout != HISQ_LAYOUT_COLOUR)
+        return fail(HISQ_EINVAL, "bad layout %d", layout);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const bool r14 = naik == HISQ_NAIK_R14;
+    const bool cm = layout == HISQ_LAYOUT_COLOUR;
     Tile t;
     if (prec == HISQ_PREC_F64) {
         DslashArgs<double> a{};
@@ -1026,8 +1044,8 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
         a.links = link_block<double>(packed, lat.Vh, false, out_parity);
         a.in = reinterpret_cast<const d2*>(in);
         a.out = reinterpret_cast<d2*>(out);
-        if ((rc = get_tile(lat, nrhs, prec, false, a, s, &t))) return rc;
-        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s));
+        if ((rc = get_tile(lat, nrhs, prec, false, a, s, &t, EPI_PLAIN, cm))) return rc;
+        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s, cm));
     } else {
         DslashArgs<float> a{};
         a.lat = lat;
@@ -1035,8 +1053,8 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
         a.links = link_block<float>(packed, lat.Vh, r14, out_parity);
         a.in = reinterpret_cast<const f2*>(in);
         a.out = reinterpret_cast<f2*>(out);
-        if ((rc = get_tile(lat, nrhs, prec, r14, a, s, &t))) return rc;
-        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, r14, t, a, s));
+        if ((rc = get_tile(lat, nrhs, prec, r14, a, s, &t, EPI_PLAIN, cm))) return rc;
+        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, r14, t, a, s, cm));
     }
     return HISQ_OK;
 }
@@ -1098,10 +1116,10 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     a.links = link_block<double>(links64, lat.Vh, false, 1);
     a.in = reinterpret_cast<const d2*>(x_e);
     a.out = w.tx;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s));
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s, false));  // caller's site-major fields
     a.in = y;
     a.out = w.sy;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s));
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s, false));
     HIP_TRY(launch_force(lat, nrhs, reinterpret_cast<const d2*>(x_e), y, w.tx, w.sy,
                          reinterpret_cast<d2*>(grad_U), reinterpret_cast<d2*>(grad_N), s));
     HIP_TRY(launch_redot(y, reinterpret_cast<const d2*>(x_e), lat.Vh, nrhs, -8.0 * mass, grad_m,
@@ -1151,8 +1169,10 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
         q.m4 = 4.0 * q.mass * q.mass;
         q.links64 = probs[j].links64;
         q.links32 = probs[j].links32;
-        q.b = reinterpret_cast<const d2*>(probs[j].b);
-        q.x = reinterpret_cast<d2*>(probs[j].x);
+        q.ub = reinterpret_cast<const d2*>(probs[j].b);
+        q.ux = reinterpret_cast<d2*>(probs[j].x);
+        q.b = w[j].bc;
+        q.x = w[j].xc;
         q.w = w[j];
         E.P.push_back(q);
     }

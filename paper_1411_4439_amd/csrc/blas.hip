@@ -6,6 +6,7 @@ namespace hisq {
 
 // ---------------------------------------------------------------------------
 // p = r + beta_k p for every active rhs k; |p_k|^2 summed in FP64 -> pp[k].
+// (site-tiled form, colour-major fields: bundles the streaming form does not cover)
 template <typename T, int NRHS, int NR>
 __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, int nblk, int bid)
 {
@@ -30,12 +31,14 @@ __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, 
     }
     const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
     if (i < a.lat.Vh && any_act) {
-        const int base = i * 3 * NRHS + g * NR;
+        using Lay = Layout<NRHS, true>;
+        const int base = Lay::site(i) + g * NR;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            const int off = base + Lay::colour(c, a.lat.Vh);
             C rv[NR], pv[NR];
-            load_rhs<NR>(a.r + base + c * NRHS, rv);
-            load_rhs<NR>(a.p + base + c * NRHS, pv);
+            load_rhs<NR>(a.r + off, rv);
+            load_rhs<NR>(a.p + off, pv);
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 // beta = 0 starts (or restarts) the recursion: p = r exactly, even
@@ -45,7 +48,7 @@ __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, 
                                             : C{rv[k].x + beta[k] * pv[k].x, rv[k].y + beta[k] * pv[k].y};
                 part[k] += (double)pv[k].x * pv[k].x + (double)pv[k].y * pv[k].y;
             }
-            store_rhs<NR>(a.p + base + c * NRHS, pv);
+            store_rhs<NR>(a.p + off, pv);
         }
     }
     double total;
@@ -351,7 +354,42 @@ hipError_t launch_zero_sel(d2* v, size_t ncplx, int nrhs, const CgState* st, hip
 }
 
 // ---------------------------------------------------------------------------
-// Per-rhs |v_k|^2 of an FP64 half field, one thread per site.
+// Layout conversions between the canonical site-major field [Vh][3][n] and the
+// solver's colour-major field [3][Vh][n] (FP64).
+__global__ void k_to_colour_major(const d2* __restrict__ src, d2* __restrict__ dst, int Vh, int nrhs)
+{
+    const size_t total = (size_t)Vh * 3 * nrhs;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = e % nrhs, rest = e / nrhs;  // dst index = (c * Vh + i) * n + k
+        const size_t i = rest % Vh, c = rest / Vh;
+        dst[e] = src[(i * 3 + c) * nrhs + k];
+    }
+}
+
+__global__ void k_to_site_major(const d2* __restrict__ src, d2* __restrict__ dst, int Vh, int nrhs)
+{
+    const size_t total = (size_t)Vh * 3 * nrhs;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = e % nrhs, rest = e / nrhs;  // dst index = (i * 3 + c) * n + k
+        const size_t c = rest % 3, i = rest / 3;
+        dst[e] = src[(c * Vh + i) * nrhs + k];
+    }
+}
+
+hipError_t launch_layout(const d2* src, d2* dst, int Vh, int nrhs, bool to_colour_major, hipStream_t s)
+{
+    const size_t total = (size_t)Vh * 3 * nrhs;
+    if (to_colour_major)
+        hipLaunchKernelGGL(k_to_colour_major, dim3(blocks_for(total, 256)), dim3(256), 0, s, src, dst, Vh, nrhs);
+    else
+        hipLaunchKernelGGL(k_to_site_major, dim3(blocks_for(total, 256)), dim3(256), 0, s, src, dst, Vh, nrhs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-rhs |v_k|^2 of an FP64 colour-major half field, one thread per site.
 template <int NRHS>
 __global__ __launch_bounds__(kMaxBlock) void k_norm2(const d2* __restrict__ v, int Vh, double* out,
                                                      double* red, uint32_t* cnt)
@@ -365,7 +403,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_norm2(const d2* __restrict__ v, i
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) {
-                const d2 e = v[((size_t)i * 3 + c) * NRHS + k];
+                const d2 e = v[((size_t)c * Vh + i) * NRHS + k];
                 part[k] += e.x * e.x + e.y * e.y;
             }
     }

@@ -5,7 +5,7 @@
 namespace hisq {
 
 #define HISQ_DECL(P, E, T) \
-    hipError_t launch_dslash_p##P##_e##E(int nrhs, const Tile& t, const DslashArgs<T>& a, hipStream_t s);
+    hipError_t launch_dslash_p##P##_e##E(int nrhs, const Tile& t, const DslashArgs<T>& a, hipStream_t s, bool cm);
 HISQ_DECL(0, 0, double)
 HISQ_DECL(0, 1, double)
 HISQ_DECL(0, 2, double)
@@ -48,35 +48,35 @@ hipError_t launch_dslash_batched_f32(int epi, bool r14, const BatchTable<float>*
 }
 
 hipError_t launch_dslash_f64(int epi, int nrhs, const Tile& t, const DslashArgs<double>& a,
-                             hipStream_t s)
+                             hipStream_t s, bool cm)
 {
     switch (epi) {
-    case EPI_PLAIN: return launch_dslash_p0_e0(nrhs, t, a, s);
-    case EPI_NORM: return launch_dslash_p0_e1(nrhs, t, a, s);
-    case EPI_CG: return launch_dslash_p0_e2(nrhs, t, a, s);
-    case EPI_RESID: return launch_dslash_p0_e3(nrhs, t, a, s);
+    case EPI_PLAIN: return launch_dslash_p0_e0(nrhs, t, a, s, cm);
+    case EPI_NORM: return launch_dslash_p0_e1(nrhs, t, a, s, cm);
+    case EPI_CG: return launch_dslash_p0_e2(nrhs, t, a, s, cm);
+    case EPI_RESID: return launch_dslash_p0_e3(nrhs, t, a, s, cm);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_dslash_f32(int epi, int nrhs, const Tile& t, const DslashArgs<float>& a,
-                             hipStream_t s)
+                             hipStream_t s, bool cm)
 {
     switch (epi) {
-    case EPI_PLAIN: return launch_dslash_p1_e0(nrhs, t, a, s);
-    case EPI_NORM: return launch_dslash_p1_e1(nrhs, t, a, s);
-    case EPI_CG: return launch_dslash_p1_e2(nrhs, t, a, s);
+    case EPI_PLAIN: return launch_dslash_p1_e0(nrhs, t, a, s, cm);
+    case EPI_NORM: return launch_dslash_p1_e1(nrhs, t, a, s, cm);
+    case EPI_CG: return launch_dslash_p1_e2(nrhs, t, a, s, cm);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_dslash_f32r14(int epi, int nrhs, const Tile& t, const DslashArgs<float>& a,
-                                hipStream_t s)
+                                hipStream_t s, bool cm)
 {
     switch (epi) {
-    case EPI_PLAIN: return launch_dslash_p2_e0(nrhs, t, a, s);
-    case EPI_NORM: return launch_dslash_p2_e1(nrhs, t, a, s);
-    case EPI_CG: return launch_dslash_p2_e2(nrhs, t, a, s);
+    case EPI_PLAIN: return launch_dslash_p2_e0(nrhs, t, a, s, cm);
+    case EPI_NORM: return launch_dslash_p2_e1(nrhs, t, a, s, cm);
+    case EPI_CG: return launch_dslash_p2_e2(nrhs, t, a, s, cm);
     default: return hipErrorInvalidValue;
     }
 }

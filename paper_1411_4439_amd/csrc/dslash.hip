@@ -88,13 +88,14 @@ __device__ __forceinline__ void load_link(const cplx<T>* __restrict__ lk, int Vh
     for (int e = 0; e < ne; ++e) m[e] = __builtin_nontemporal_load(lp + e * Vh);
 }
 
-template <typename T, int NRHS, int NR>
-__device__ __forceinline__ void load_vec(const cplx<T>* __restrict__ in, int nbr, int g,
+template <typename T, int NRHS, int NR, bool CM>
+__device__ __forceinline__ void load_vec(const cplx<T>* __restrict__ in, int Vh, int nbr, int g,
                                          cplx<T> (&v)[3][NR])
 {
-    const cplx<T>* vp = in + (nbr * 3) * NRHS + g * NR;
+    using Lay = Layout<NRHS, CM>;
+    const cplx<T>* vp = in + Lay::site(nbr) + g * NR;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + b * NRHS, v[b]);
+    for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + Lay::colour(b, Vh), v[b]);
 }
 
 template <typename T, int NR, bool R14, int S>
@@ -161,7 +162,7 @@ __device__ __forceinline__ int neighbour(const Lat& lat, const SiteCoord& sc)
 // HBM and see the longest latency; neighbour vectors mostly hit L2).  The
 // scheduling barriers keep the compiler from hoisting further loads, which
 // would otherwise exhaust the register file.
-template <typename T, int NRHS, int NR, bool R14>
+template <typename T, int NRHS, int NR, bool R14, bool CM>
 __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
                                             const cplx<T>* __restrict__ lk,
                                             const cplx<T>* __restrict__ in,
@@ -185,11 +186,12 @@ __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
     C v[2][3][NR];
     load_link<T, R14, 0>(lk, Vh, i, m[0]);
     if constexpr (LD == 2) load_link<T, R14, 1>(lk, Vh, i, m[1]);
-    load_vec<T, NRHS, NR>(in, neighbour<0>(lat, sc), g, v[0]);
+    load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<0>(lat, sc), g, v[0]);
     static_for<0, 16>([&](auto S) {
         constexpr int s = decltype(S)::value;
         if constexpr (s + LD < 16) load_link<T, R14, s + LD>(lk, Vh, i, m[(s + LD) % (LD + 1)]);
-        if constexpr (s + 1 < 16) load_vec<T, NRHS, NR>(in, neighbour<s + 1>(lat, sc), g, v[(s + 1) & 1]);
+        if constexpr (s + 1 < 16)
+            load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<s + 1>(lat, sc), g, v[(s + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         apply_slot<T, NR, R14, s>(m[s % (LD + 1)], v[s & 1], acc);
         __builtin_amdgcn_sched_barrier(0);
@@ -253,7 +255,7 @@ __device__ __forceinline__ double norm2c(cplx<T> v)
 // One tile (one work-group's worth of sites) of a half-Dslash with epilogue
 // EPI; `tile` is the tile index, the problem's grid has nblk work-groups and
 // this one is number bid (for the reductions).
-template <typename T, int NRHS, int NR, bool R14, int EPI>
+template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM>
 __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, int nblk, int bid)
 {
     using C = cplx<T>;
@@ -290,13 +292,14 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
     const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
     if (i < a.lat.Vh) {
         C acc[3][NR];
-        dslash_site<T, NRHS, NR, R14>(a.lat, a.parity, i, g, a.links, a.in, acc);
+        dslash_site<T, NRHS, NR, R14, CM>(a.lat, a.parity, i, g, a.links, a.in, acc);
         pin_acc(acc);
-        const int base = i * 3 * NRHS + g * NR;
+        using Lay = Layout<NRHS, CM>;
+        const int base = Lay::site(i) + g * NR;
         if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                store_rhs<NR>(a.out + base + c * NRHS, acc[c]);
+                store_rhs<NR>(a.out + base + Lay::colour(c, a.lat.Vh), acc[c]);
                 if constexpr (EPI == EPI_NORM) {
 #pragma unroll
                     for (int k = 0; k < NR; ++k) part[k] += norm2c<T>(acc[c][k]);
@@ -307,9 +310,9 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 C pv[NR], xv[NR], rv[NR];
-                load_rhs<NR>(a.p + base + c * NRHS, pv);
-                load_rhs<NR>(a.x + base + c * NRHS, xv);
-                load_rhs<NR>(a.r + base + c * NRHS, rv);
+                load_rhs<NR>(a.p + base + Lay::colour(c, a.lat.Vh), pv);
+                load_rhs<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
+                load_rhs<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     const C q = C{m4 * pv[k].x - acc[c][k].x, m4 * pv[k].y - acc[c][k].y};
@@ -319,8 +322,8 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
                     }
                     part[k] += norm2c<T>(rv[k]);
                 }
-                store_rhs<NR>(a.x + base + c * NRHS, xv);
-                store_rhs<NR>(a.r + base + c * NRHS, rv);
+                store_rhs<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
+                store_rhs<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
             }
             }
         } else if constexpr (EPI == EPI_RESID) {
@@ -328,14 +331,14 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 d2 bv[NR], xv[NR];
-                load_rhs<NR>(a.b + base + c * NRHS, bv);
-                load_rhs<NR>(a.xh + base + c * NRHS, xv);
+                load_rhs<NR>(a.b + base + Lay::colour(c, a.lat.Vh), bv);
+                load_rhs<NR>(a.xh + base + Lay::colour(c, a.lat.Vh), xv);
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     const d2 rv = d2{bv[k].x - (m4 * xv[k].x - acc[c][k].x),
                                      bv[k].y - (m4 * xv[k].y - acc[c][k].y)};
                     part[k] += norm2c<double>(rv);
-                    if (act[k]) a.out[base + c * NRHS + k] = rv;
+                    if (act[k]) a.out[base + Lay::colour(c, a.lat.Vh) + k] = rv;
                 }
             }
             }
@@ -356,10 +359,10 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 #define HISQ_KATTR
 #endif
 
-template <typename T, int NRHS, int NR, bool R14, int EPI>
+template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM>
 __global__ __launch_bounds__(kMaxBlock) HISQ_KATTR void k_dslash(const DslashArgs<T> a)
 {
-    dslash_tile<T, NRHS, NR, R14, EPI>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat.L[3]), gridDim.x,
+    dslash_tile<T, NRHS, NR, R14, EPI, CM>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat.L[3]), gridDim.x,
                                        blockIdx.x);
 }
 
@@ -378,43 +381,49 @@ __global__ __launch_bounds__(kMaxBlock) void k_dslash_batched(const BatchTable<T
     const DslashArgs<T>& a = EPI == EPI_NORM ? bp.k2 : bp.k3;
     const int nb = bp.nblocks;
     switch (bp.n * 16 + bp.nr) {
-    case 1 * 16 + 1: dslash_tile<T, 1, 1, R14, EPI>(a, bid, nb, bid); break;
-    case 2 * 16 + 2: dslash_tile<T, 2, 2, R14, EPI>(a, bid, nb, bid); break;
-    case 2 * 16 + 1: dslash_tile<T, 2, 1, R14, EPI>(a, bid, nb, bid); break;
-    case 3 * 16 + 3: dslash_tile<T, 3, 3, R14, EPI>(a, bid, nb, bid); break;
-    case 4 * 16 + 4: dslash_tile<T, 4, 4, R14, EPI>(a, bid, nb, bid); break;
-    case 4 * 16 + 2: dslash_tile<T, 4, 2, R14, EPI>(a, bid, nb, bid); break;
-    case 5 * 16 + 5: dslash_tile<T, 5, 5, R14, EPI>(a, bid, nb, bid); break;
-    case 6 * 16 + 6: dslash_tile<T, 6, 6, R14, EPI>(a, bid, nb, bid); break;
-    case 6 * 16 + 3: dslash_tile<T, 6, 3, R14, EPI>(a, bid, nb, bid); break;
-    case 7 * 16 + 7: dslash_tile<T, 7, 7, R14, EPI>(a, bid, nb, bid); break;
-    case 8 * 16 + 8: dslash_tile<T, 8, 8, R14, EPI>(a, bid, nb, bid); break;
-    case 8 * 16 + 4: dslash_tile<T, 8, 4, R14, EPI>(a, bid, nb, bid); break;
+    case 1 * 16 + 1: dslash_tile<T, 1, 1, R14, EPI, true>(a, bid, nb, bid); break;
+    case 2 * 16 + 2: dslash_tile<T, 2, 2, R14, EPI, true>(a, bid, nb, bid); break;
+    case 2 * 16 + 1: dslash_tile<T, 2, 1, R14, EPI, true>(a, bid, nb, bid); break;
+    case 3 * 16 + 3: dslash_tile<T, 3, 3, R14, EPI, true>(a, bid, nb, bid); break;
+    case 4 * 16 + 4: dslash_tile<T, 4, 4, R14, EPI, true>(a, bid, nb, bid); break;
+    case 4 * 16 + 2: dslash_tile<T, 4, 2, R14, EPI, true>(a, bid, nb, bid); break;
+    case 5 * 16 + 5: dslash_tile<T, 5, 5, R14, EPI, true>(a, bid, nb, bid); break;
+    case 6 * 16 + 6: dslash_tile<T, 6, 6, R14, EPI, true>(a, bid, nb, bid); break;
+    case 6 * 16 + 3: dslash_tile<T, 6, 3, R14, EPI, true>(a, bid, nb, bid); break;
+    case 7 * 16 + 7: dslash_tile<T, 7, 7, R14, EPI, true>(a, bid, nb, bid); break;
+    case 8 * 16 + 8: dslash_tile<T, 8, 8, R14, EPI, true>(a, bid, nb, bid); break;
+    case 8 * 16 + 4: dslash_tile<T, 8, 4, R14, EPI, true>(a, bid, nb, bid); break;
     default: break;
     }
 }
 
 template <typename T, bool R14, int EPI, int NRHS, int NR>
-static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s)
+static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s, bool cm)
 {
     constexpr int G = NRHS / NR;
     const long threads = (long)a.lat.Vh * G;
     a.ntiles = (int)((threads + t.bs - 1) / t.bs);
     a.remap = t.remap;
-    hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
+    // the solver's kernels exist in colour-major form only; the plain Dslash in both
+    if (cm)
+        hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI, true>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
+    else if constexpr (EPI == EPI_PLAIN)
+        hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI, false>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
 template <typename T, bool R14, int EPI, int NRHS>
-static hipError_t pick_nr(const Tile& t, const DslashArgs<T>& a, hipStream_t s)
+static hipError_t pick_nr(const Tile& t, const DslashArgs<T>& a, hipStream_t s, bool cm)
 {
-    if (t.nr == NRHS) return go<T, R14, EPI, NRHS, NRHS>(t, a, s);
+    if (t.nr == NRHS) return go<T, R14, EPI, NRHS, NRHS>(t, a, s, cm);
     if constexpr (NRHS % 2 == 0)
-        if (t.nr == NRHS / 2) return go<T, R14, EPI, NRHS, NRHS / 2>(t, a, s);
+        if (t.nr == NRHS / 2) return go<T, R14, EPI, NRHS, NRHS / 2>(t, a, s, cm);
     if constexpr (NRHS % 4 == 0)
-        if (t.nr == NRHS / 4) return go<T, R14, EPI, NRHS, NRHS / 4>(t, a, s);
+        if (t.nr == NRHS / 4) return go<T, R14, EPI, NRHS, NRHS / 4>(t, a, s, cm);
     if constexpr (NRHS % 8 == 0)
-        if (t.nr == NRHS / 8) return go<T, R14, EPI, NRHS, NRHS / 8>(t, a, s);
+        if (t.nr == NRHS / 8) return go<T, R14, EPI, NRHS, NRHS / 8>(t, a, s, cm);
     return hipErrorInvalidValue;
 }
 
@@ -422,21 +431,21 @@ static hipError_t pick_nr(const Tile& t, const DslashArgs<T>& a, hipStream_t s)
 #define HISQ_CAT(a, b) HISQ_CAT2(a, b)
 #define HISQ_LAUNCH_NAME HISQ_CAT(HISQ_CAT(HISQ_CAT(launch_dslash_p, HISQ_KPREC), _e), HISQ_KEPI)
 
-hipError_t HISQ_LAUNCH_NAME(int nrhs, const Tile& t, const DslashArgs<KT>& a, hipStream_t s)
+hipError_t HISQ_LAUNCH_NAME(int nrhs, const Tile& t, const DslashArgs<KT>& a, hipStream_t s, bool cm)
 {
     constexpr int EPI = HISQ_KEPI;
     if constexpr (EPI == EPI_RESID && HISQ_KPREC != 0) {
         return hipErrorInvalidValue;
     } else {
         switch (nrhs) {
-        case 1: return pick_nr<KT, kR14, EPI, 1>(t, a, s);
-        case 2: return pick_nr<KT, kR14, EPI, 2>(t, a, s);
-        case 3: return pick_nr<KT, kR14, EPI, 3>(t, a, s);
-        case 4: return pick_nr<KT, kR14, EPI, 4>(t, a, s);
-        case 5: return pick_nr<KT, kR14, EPI, 5>(t, a, s);
-        case 6: return pick_nr<KT, kR14, EPI, 6>(t, a, s);
-        case 7: return pick_nr<KT, kR14, EPI, 7>(t, a, s);
-        case 8: return pick_nr<KT, kR14, EPI, 8>(t, a, s);
+        case 1: return pick_nr<KT, kR14, EPI, 1>(t, a, s, cm);
+        case 2: return pick_nr<KT, kR14, EPI, 2>(t, a, s, cm);
+        case 3: return pick_nr<KT, kR14, EPI, 3>(t, a, s, cm);
+        case 4: return pick_nr<KT, kR14, EPI, 4>(t, a, s, cm);
+        case 5: return pick_nr<KT, kR14, EPI, 5>(t, a, s, cm);
+        case 6: return pick_nr<KT, kR14, EPI, 6>(t, a, s, cm);
+        case 7: return pick_nr<KT, kR14, EPI, 7>(t, a, s, cm);
+        case 8: return pick_nr<KT, kR14, EPI, 8>(t, a, s, cm);
         default: return hipErrorInvalidValue;
         }
     }

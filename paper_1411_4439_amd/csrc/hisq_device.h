@@ -158,6 +158,19 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
 
 __device__ inline bool finite_d(double v) { return v - v == 0.0; }
 
+// Spinor field layouts, element (site i, colour c, rhs k) of an n-rhs field:
+//   site-major   [Vh][3][n]  (CM = false, the canonical layout at the boundary)
+//   colour-major [3][Vh][n]  (CM = true, the solver's internal layout)
+// Both keep the rhs of a site innermost.  In colour-major order the lanes of a
+// wave, which own consecutive sites, read one contiguous stretch per colour;
+// in site-major order they stride by 3n complex numbers, and every load
+// instruction touches about three times as many cache lines.
+template <int NRHS, bool CM>
+struct Layout {
+    __device__ static __forceinline__ int site(int i) { return CM ? i * NRHS : i * 3 * NRHS; }
+    __device__ static __forceinline__ int colour(int c, int Vh) { return CM ? c * Vh * NRHS : c * NRHS; }
+};
+
 // Loads and stores of NR consecutive complex numbers (rhs of one colour).
 template <int NR>
 __device__ __forceinline__ void load_rhs(const f2* __restrict__ p, f2 (&v)[NR])

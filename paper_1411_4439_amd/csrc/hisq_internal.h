@@ -185,13 +185,15 @@ struct Tile {
 inline size_t red_doubles(size_t blocks) { return (blocks + (blocks + 63) / 64) * kMaxRhs; }
 inline size_t red_counters(size_t blocks) { return 1 + (blocks + 63) / 64; }
 
-// Launchers, defined in the per-precision kernel objects.
+// Launchers, defined in the per-precision kernel objects.  cm selects the
+// colour-major field layout [3][Vh][n] (the solver's); the plain Dslash also
+// exists for the site-major canonical layout [Vh][3][n].
 hipError_t launch_dslash_f64(int epi, int nrhs, const Tile& t, const DslashArgs<double>& a,
-                             hipStream_t s);
+                             hipStream_t s, bool cm);
 hipError_t launch_dslash_f32(int epi, int nrhs, const Tile& t, const DslashArgs<float>& a,
-                             hipStream_t s);
+                             hipStream_t s, bool cm);
 hipError_t launch_dslash_f32r14(int epi, int nrhs, const Tile& t, const DslashArgs<float>& a,
-                                hipStream_t s);
+                                hipStream_t s, bool cm);
 hipError_t launch_dslash_batched_f64(int epi, const BatchTable<double>* tab, int total_blocks,
                                      int bs, hipStream_t s);
 hipError_t launch_dslash_batched_f32(int epi, bool r14, const BatchTable<float>* tab,
@@ -214,6 +216,7 @@ hipError_t launch_pupdate_f32(int nrhs, const Tile& t, const PupdateArgs<float>&
 // Elementwise and reduction helpers (blas.hip).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_state_reset(CgState* st, int nrhs, int active, hipStream_t s);
+// per-rhs |v|^2 of a colour-major FP64 field
 hipError_t launch_norm2_f64(const d2* v, int Vh, int nrhs, double* out, double* red,
                             uint32_t* cnt, hipStream_t s);
 hipError_t launch_to_f32_sel(const d2* src, f2* dst, size_t ncplx, int nrhs, const CgState* st,
@@ -221,6 +224,7 @@ hipError_t launch_to_f32_sel(const d2* src, f2* dst, size_t ncplx, int nrhs, con
 hipError_t launch_accum_sel(d2* xh, f2* xl, size_t ncplx, int nrhs, const CgState* st,
                             hipStream_t s);
 hipError_t launch_copy_f64(const d2* src, d2* dst, size_t ncplx, hipStream_t s);
+hipError_t launch_layout(const d2* src, d2* dst, int Vh, int nrhs, bool to_colour_major, hipStream_t s);
 hipError_t launch_zero_sel(d2* v, size_t ncplx, int nrhs, const CgState* st, hipStream_t s);
 hipError_t launch_redot(const d2* y, const d2* x, int Vh, int nrhs, double scale, double* out,
                         double* red, uint32_t* cnt, hipStream_t s);

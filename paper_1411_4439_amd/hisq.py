@@ -29,6 +29,7 @@ HISQ_MAX_RHS, HISQ_MAX_PROBLEMS = 8, 16
 PREC_F64, PREC_F32 = 0, 1
 NAIK_FULL, NAIK_R14 = 0, 1
 MODE_FP64, MODE_MIXED = 0, 1
+LAYOUT_SITE, LAYOUT_COLOUR = 0, 1
 K_PUPDATE, K_DSLASH_OE, K_DSLASH_EO, K_RELIABLE = 0, 1, 2, 3
 
 
@@ -82,7 +83,7 @@ _sig = {
                                                        ctypes.c_int]),
     "hisq_pack_links": (ctypes.c_int, [_G, _P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "hisq_dslash": (ctypes.c_int, [_G, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                   _P, _P, _P, _P]),
+                                   ctypes.c_int, _P, _P, _P, _P]),
     "hisq_cg_solve": (ctypes.c_int, [_G, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Params),
                                      _P, _P, _P, _P, _P, ctypes.c_size_t, ctypes.POINTER(Info), _P]),
     "hisq_cg_solve_backward": (ctypes.c_int, [_G, ctypes.c_double, ctypes.c_int,
@@ -178,10 +179,10 @@ def hisq_pack_links(L, U, N, prec, naik, packed, stream=None):
                                        _ptr(packed), _stream(stream)), "hisq_pack_links")
 
 
-def hisq_dslash(L, out_parity, nrhs, prec, naik, packed, vin, vout, stream=None):
+def hisq_dslash(L, out_parity, nrhs, prec, naik, layout, packed, vin, vout, stream=None):
     _dev_tensor(vin, "in")
     _dev_tensor(vout, "out")
-    return _check(_lib.hisq_dslash(ctypes.byref(geom(L)), out_parity, nrhs, prec, naik,
+    return _check(_lib.hisq_dslash(ctypes.byref(geom(L)), out_parity, nrhs, prec, naik, layout,
                                    _ptr(packed), _ptr(vin), _ptr(vout), _stream(stream)),
                   "hisq_dslash")
 
@@ -256,10 +257,11 @@ class Links:
         return self.f32r14 if naik == NAIK_R14 else self.f32
 
 
-def dslash(links, out_parity, v, prec=PREC_F64, naik=NAIK_FULL, stream=None):
-    """D_{out, 1-out} v for a half field v [Vh][3][n] (complex128 or complex64)."""
+def dslash(links, out_parity, v, prec=PREC_F64, naik=NAIK_FULL, stream=None, layout=LAYOUT_SITE):
+    """D_{out, 1-out} v for a half field v (complex128 or complex64), shaped
+    [Vh][3][n] for LAYOUT_SITE or [3][Vh][n] for LAYOUT_COLOUR."""
     out = v.new_empty(v.shape)
-    hisq_dslash(links.L, out_parity, v.shape[2], prec, naik, links.packed(prec, naik),
+    hisq_dslash(links.L, out_parity, v.shape[2], prec, naik, layout, links.packed(prec, naik),
                 v.contiguous(), out, stream)
     return out
 

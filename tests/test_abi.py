@@ -105,8 +105,10 @@ def test_errors_before_any_launch(H):
     rc = lib.hisq_cg_solve(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, fake, fake,
                            fake, 16, ctypes.byref(info), None)
     assert rc == H.HISQ_EWORKSPACE
-    rc = lib.hisq_dslash(ctypes.byref(g), 2, 1, H.PREC_F64, H.NAIK_FULL, fake, fake, fake, None)
+    rc = lib.hisq_dslash(ctypes.byref(g), 2, 1, H.PREC_F64, H.NAIK_FULL, 0, fake, fake, fake, None)
     assert rc == H.HISQ_EINVAL
+    rc = lib.hisq_dslash(ctypes.byref(g), 0, 1, H.PREC_F64, H.NAIK_FULL, 2, fake, fake, fake, None)
+    assert rc == H.HISQ_EINVAL and "layout" in H.hisq_last_error()
     rc = lib.hisq_pack_links(ctypes.byref(g), fake, fake, H.PREC_F64, H.NAIK_R14, fake, None)
     assert rc == H.HISQ_EINVAL
     rc = lib.hisq_cg_solve_batched(0, None, ctypes.byref(p), fake, 0, None, None)
@@ -127,4 +129,5 @@ def test_solver_refuses_host_tensors(H):
     L = (4, 4, 4, 4)
     b = torch.zeros((128, 3, 1), dtype=torch.complex128)
     with pytest.raises(ValueError):
-        H.hisq_dslash(L, 0, 1, H.PREC_F64, H.NAIK_FULL, torch.zeros(16, dtype=torch.uint8), b, b)
+        H.hisq_dslash(L, 0, 1, H.PREC_F64, H.NAIK_FULL, H.LAYOUT_SITE,
+                      torch.zeros(16, dtype=torch.uint8), b, b)

@@ -1,9 +1,10 @@
 """GPU half-Dslash (Sec. 1, eqs. (3)-(4)) against the FP64 CPU oracle.
 
 FP64 within 1e-13 and FP32 (full or r14 Naik) within 1e-6 relative L2 per rhs,
-for n = 1..8, both output parities, every rhs-per-thread tile and work-group
-size, on lattices with wrap aliasing (L = 4: x+3 = x-1; L = 6: x+3 = x-3) and
-with ragged last tiles.
+for n = 1..8, both output parities, both field orders (site-major [Vh][3][n]
+and colour-major [3][Vh][n]), every rhs-per-thread tile and work-group size, on
+lattices with wrap aliasing (L = 4: x+3 = x-1; L = 6: x+3 = x-3) and with
+ragged last tiles.
 """
 import numpy as np
 import pytest
@@ -29,6 +30,16 @@ def _source(L, n, seed):
     return W.make_sources(L, n, seed)
 
 
+def _apply(H, links, parity, v, prec, nk=0, layout=0):
+    """Dslash of a site-major numpy field through the given field order; the
+    result comes back site-major."""
+    if layout == H.LAYOUT_COLOUR:
+        got = H.dslash(links, parity, dev(np.ascontiguousarray(v.transpose(1, 0, 2))), prec, nk,
+                       layout=layout)
+        return np.ascontiguousarray(host(got).transpose(1, 0, 2))
+    return host(H.dslash(links, parity, dev(v), prec, nk))
+
+
 def _tiles(n):
     return [n // g for g in (1, 2, 4, 8) if n % g == 0]
 
@@ -51,13 +62,14 @@ def test_dslash_f64_all_tiles(L, n):
         outs = []
         for nr in _tiles(n):
             for bs, order in ((64, 0), (64, 2), (256, 1), (256, 2)):
-                say("f64", L, n, parity, nr, bs, order)
-                H.hisq_set_tuning(1, nr, bs, order)
-                got = host(H.dslash(links, parity, dev(v), H.PREC_F64))
-                assert rel_l2_per_rhs(got, want) <= 1e-13, (nr, bs, order)
-                outs.append(got)
-        # the per-site arithmetic order depends on neither the tile nor the tile
-        # order: bitwise equal
+                for lay in (H.LAYOUT_SITE, H.LAYOUT_COLOUR):
+                    say("f64", L, n, parity, nr, bs, order, lay)
+                    H.hisq_set_tuning(1, nr, bs, order)
+                    got = _apply(H, links, parity, v, H.PREC_F64, layout=lay)
+                    assert rel_l2_per_rhs(got, want) <= 1e-13, (nr, bs, order, lay)
+                    outs.append(got)
+        # the per-site arithmetic order depends on neither the tile, the tile
+        # order nor the field order: bitwise equal
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
 
@@ -73,11 +85,11 @@ def test_dslash_f32_all_tiles(L, n, naik):
         v = _source(L, n, 200 + n + parity).astype(np.complex64)
         want = oracle.dslash_eo(L, U, N, v.astype(np.complex128), parity)
         for nr in _tiles(n):
-            for bs, order in ((64, 2), (128, 1)):
-                say("f32", naik, L, n, parity, nr, bs, order)
+            for bs, order, lay in ((64, 2, 0), (128, 1, 0), (64, 2, 1), (128, 1, 1)):
+                say("f32", naik, L, n, parity, nr, bs, order, lay)
                 H.hisq_set_tuning(1, nr, bs, order)
-                got = host(H.dslash(links, parity, dev(v), H.PREC_F32, nk)).astype(np.complex128)
-                assert rel_l2_per_rhs(got, want) <= 1e-6, (nr, bs, order)
+                got = _apply(H, links, parity, v, H.PREC_F32, nk, lay).astype(np.complex128)
+                assert rel_l2_per_rhs(got, want) <= 1e-6, (nr, bs, order, lay)
 
 
 @pytest.mark.parametrize("c", [1.0, -1.0 / 24.0])
@@ -132,9 +144,10 @@ def test_pack_rejects_non_unitary_naik():
 
 
 def test_dslash_headline_lattice_sampled_sites():
-    """48^3 x 12, n = 8, FP32 and r14, in the autotuned launch shape the solver
-    and the benchmark use: sampled output sites against the oracle, and the
-    whole output against the FP64 GPU Dslash of the same input."""
+    """48^3 x 12, n = 8, FP32 and r14, in the autotuned launch shape and the
+    colour-major order the solver and the benchmark use (and site-major):
+    sampled output sites against the oracle, and the whole output against the
+    FP64 GPU Dslash of the same input."""
     H = gpu_lib()
     L = (48, 48, 48, 12)
     U, N = W.make_links(L, 0.2, W.links_seed(3))
@@ -150,8 +163,8 @@ def test_dslash_headline_lattice_sampled_sites():
     assert rel_l2_per_rhs(host(ref64)[sites // 2], oracle.dslash_sites(L, U, N, v, 1, sites)) <= 1e-13
     H.hisq_set_tuning(0)
     for nk in (H.NAIK_FULL, H.NAIK_R14):
-        say("headline", nk)
-        got = H.dslash(links, 1, dev(v32), H.PREC_F32, nk)
-        g = host(got).astype(np.complex128)
-        assert rel_l2_per_rhs(g[sites // 2], want) <= 1e-6
-        assert rel_l2_per_rhs(g, host(ref64)) <= 1e-6
+        for lay in (H.LAYOUT_SITE, H.LAYOUT_COLOUR):
+            say("headline", nk, lay)
+            g = _apply(H, links, 1, v32, H.PREC_F32, nk, lay).astype(np.complex128)
+            assert rel_l2_per_rhs(g[sites // 2], want) <= 1e-6
+            assert rel_l2_per_rhs(g, host(ref64)) <= 1e-6
