@@ -55,7 +55,44 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three 1 GiB device-to-device copies (the reference kernel "
+                         "that scales hardware byte counters)")
     return ap.parse_args()
+
+
+# Files whose contents decide the Dslash kernels' code: a counter summary taken
+# from other contents no longer describes the kernel.
+KERNEL_SOURCES = ("paper_1411_4439_amd/csrc/dslash.hip", "paper_1411_4439_amd/csrc/hisq_device.h",
+                  "paper_1411_4439_amd/csrc/hisq_internal.h", "paper_1411_4439_amd/build.py")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, tile):
+    """HBM bytes per launch of `kernel` from a committed hardware-counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy), or None when no summary
+    matches this kernel's current source, workload and tile."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if (kv.get("kernel") == kernel and kv.get("workload") == workload
+                and kv.get("source_sha256") == kernel_source_sha() and kv.get("tile") == tile
+                and "traffic_bytes_per_launch" in kv):
+            return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def main():
@@ -138,6 +175,11 @@ def main():
     else:
         dom = ("dslash_oe_norm", gbps_oe, bytes_oe, avg_ms[1])
     iters = infos[-1]["iters"]
+    tile = "nr=%d bs=%d order=%d" % (infos[-1]["rhs_per_thread"], infos[-1]["block_size"],
+                                     infos[-1]["tile_order"])
+    workload = ("HISQ even-odd CG, mixed FP32/FP64, %s Naik, %dx%dx%dx%d, %d rhs, m=%g"
+                % (nk, L[0], L[1], L[2], L[3], n, m))
+    traffic, traffic_src = measured_traffic(dom[0], workload, tile)
     result = {
         "metric": METRIC,
         "value": round(dslash_gbps, 1),
@@ -151,16 +193,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic (seeded links eta*exp(i*%.1f*H), N=-(1/24)UUU, Gaussian sources)" % args.eps,
-        "config": {"workload": "HISQ even-odd CG, mixed FP32/FP64, %s Naik, %dx%dx%dx%d, %d rhs, m=%g"
-                               % (nk, L[0], L[1], L[2], L[3], n, m),
+        "config": {"workload": workload,
                    "lattice": list(L), "nrhs": n, "mass": m, "tol": 1e-10, "naik": nk,
                    "parallelism": "single GPU (rhs bundles shard with no communication)"},
         "pct_hbm_peak": round(100 * dslash_gbps / HBM_PEAK_GBPS, 1),
         "dslash_gflops": round(dslash_gflops, 1),
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(dom[1], 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(dom[1] / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "algorithmic_bytes_per_launch": dom[2], "avg_launch_ms": round(dom[3], 5)},
+                     "frac": round(dom[1] / HBM_PEAK_GBPS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "traffic_source": traffic_src,
+                     "algorithmic_bytes_per_launch": dom[2], "avg_launch_ms": round(dom[3], 5),
+                     "tile": tile, "kernel_source_sha256": kernel_source_sha()},
         "kernels": {"dslash_oe_norm": {"avg_ms": round(avg_ms[1], 5), "GBps": round(gbps_oe, 1),
                                        "launches": tot_n[1]},
                     "dslash_eo_cg_epilogue": {"avg_ms": round(avg_ms[2], 5), "GBps": round(gbps_eo, 1),
@@ -250,6 +294,14 @@ def main():
                                   "sample": "%d FP64 half-Dslash applications, %s, %d rhs (%.1f s each)"
                                             % (reps, "x".join(map(str, L)), n, cpu_s)}
     print(json.dumps(result), flush=True)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB device-to-device copies done")
 
 
 if __name__ == "__main__":

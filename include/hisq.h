@@ -113,7 +113,9 @@ typedef struct {
     int32_t total_iters;                 /* iterations of the bundle (max over rhs)     */
     int32_t block_size;                  /* tuned work-group size of the Dslash         */
     int32_t rhs_per_thread;              /* tuned rhs tile of the Dslash                */
-    int32_t tile_order;                  /* tuned work-group -> tile order (0, 1, 2)    */
+    int32_t tile_order;                  /* tuned work-group -> tile order (0..3)       */
+    int32_t stage_rows;                  /* tuned LDS-staged x-rows per tile (0: none)  */
+    int32_t reserved;
     double seconds;                      /* host wall time of the solve                 */
     double kernel_ms[HISQ_K_COUNT];      /* profile = 1: summed event time per class    */
     int32_t kernel_launches[HISQ_K_COUNT];
@@ -218,16 +220,26 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
 /*
  * Autotuner control (process-wide).  mode 0: time the candidate tiles on first
  * use of a (lattice, nrhs, precision, Naik, kernel) key and cache the fastest
- * (default); mode 1: always use rhs_per_thread / block_size / tile_order;
+ * (default); mode 1: always use rhs_per_thread / block_size / tile_order /
+ * stage_rows;
  * mode 2: built-in default, no timing.  rhs_per_thread must divide the bundle
  * with a power-of-two quotient (otherwise the forced tile is ignored for that
  * bundle), block_size is 64, 128 or 256, tile_order is 0 (canonical site
- * order), 1 (a contiguous slab of tiles per XCD) or 2 (per XCD, the time
+ * order), 1 (a contiguous slab of tiles per XCD), 2 (per XCD, the time
  * slices of one slice position back to back; falls back to 1 where tiles
- * would straddle a time slice).  The order only changes cache locality, never
- * results.  Returns HISQ_EINVAL for an unknown mode or out-of-range values.
+ * would straddle a time slice) or 3 (XCD j owns z-chunk j of L2/8 planes and
+ * walks it x-y position outermost, then t, then z; falls back to 1 unless
+ * L2 % 8 == 0 and a tile divides an x-y plane).  stage_rows > 0 selects the
+ * LDS-staged Dslash on colour-major fields: a work-group covers stage_rows
+ * whole x-rows of one (z, t) plane (block size stage_rows * L0/2 * n /
+ * rhs_per_thread, which then replaces block_size) and reads its x and y
+ * neighbours from LDS; where that shape is not possible (block not a multiple
+ * of 64 or above 512 threads, L1 % stage_rows != 0, staged rows above 64 KB,
+ * site-major fields) the unstaged kernel runs.  Neither the order nor the
+ * staging changes results.  Returns HISQ_EINVAL for an unknown mode or
+ * out-of-range values.
  */
-int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order);
+int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order, int stage_rows);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hisq_last_error(void);

@@ -5,10 +5,12 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 package never loads the HIP library: the two share no code.
 
 ``hisq_oracle.c`` holds the arithmetic (HISQ Dslash of eq. (3) of Kaczmarek et
-al., GPUHEP2014, the even-odd operator A = 4m^2 - D_eo D_oe, CG, the link force
-and the 14-real Naik encoding); this module only compiles it with gcc and
-marshals numpy arrays through ctypes.  ``oracle.dense`` assembles the same
-operator as a dense matrix for tiny lattices.
+al., GPUHEP2014, the even-odd operator A = 4m^2 - D_eo D_oe, CG, the link force,
+the 14-real Naik encoding and the mu-derivatives of the Dslash); this module
+compiles it with gcc and marshals numpy arrays through ctypes.  The full-matrix
+solve and the trace estimator of eq. (2) below only chain those routines in the
+order the method states.  ``oracle.dense`` assembles the same operators as dense
+matrices for tiny lattices.
 """
 from __future__ import annotations
 
@@ -60,6 +62,7 @@ def _load():
             lib.orc_force.argtypes = [Lp, I, D, P, P, P, P, P, P, P]
             lib.orc_r14_pack.argtypes = [ctypes.c_long, P, P, P]
             lib.orc_r14_unpack.argtypes = [ctypes.c_long, P, P]
+            lib.orc_dslash_chem_eo.argtypes = [Lp, I, I, P, P, D, I, P, P]
             lib.orc_num_threads.argtypes = []
             _lib = lib
     return _lib
@@ -195,3 +198,50 @@ def r14_unpack(P):
     M = np.empty(lead + (3, 3), dtype=np.complex128)
     _check(_load().orc_r14_unpack(count, _ptr(P), _ptr(M)))
     return M
+
+
+def dslash_dmu(L, U, N, v, out_parity, nder, mu=0.0):
+    """d^n D(mu) / d mu^n restricted to one output parity (input parity
+    1 - out_parity); nder = 0 is D(mu).  Temporal h-hops carry exp(h mu)."""
+    U, N = _links(L, U, N)
+    v = _c128(v)
+    w = np.empty_like(v)
+    _check(_load().orc_dslash_chem_eo(_geom(L), v.shape[2], int(out_parity), _ptr(U), _ptr(N),
+                                      float(mu), int(nder), _ptr(v), _ptr(w)))
+    return w
+
+
+def apply_M(L, U, N, m, x_e, x_o, nder=0):
+    """(y_e, y_o) = d^n M / d mu^n (x_e, x_o) at mu = 0, M = 2m + D: nder = 0 is M
+    itself, nder >= 1 the derivative operators of eq. (2) (the mass term does not
+    depend on mu)."""
+    if nder == 0:
+        return (2.0 * m * _c128(x_e) + dslash_eo(L, U, N, x_o, 0),
+                2.0 * m * _c128(x_o) + dslash_eo(L, U, N, x_e, 1))
+    return dslash_dmu(L, U, N, x_o, 0, nder), dslash_dmu(L, U, N, x_e, 1, nder)
+
+
+def solve_full(L, U, N, m, b_e, b_o, tol=1e-13, maxiter=20000):
+    """x = M^{-1} b on the full lattice through the even-odd reduction:
+    (4m^2 - D_eo D_oe) x_e = 2m b_e - D_eo b_o, then x_o = (b_o - D_oe x_e) / (2m)."""
+    b_e, b_o = _c128(b_e), _c128(b_o)
+    rhs = 2.0 * m * b_e - dslash_eo(L, U, N, b_o, 0)
+    x_e, info = cg(L, U, N, m, rhs, tol=tol, maxiter=maxiter)
+    x_o = (b_o - dslash_eo(L, U, N, x_e, 1)) / (2.0 * m)
+    return x_e, x_o, info
+
+
+def trace_estimate(L, U, N, m, orders, eta_e, eta_o, tol=1e-13):
+    """Per-noise-vector terms of eq. (2):
+    eta_k^dag M^(n_1) M^{-1} M^(n_2) M^{-1} ... M^(n_j) M^{-1} eta_k for
+    orders = (n_1, ..., n_j), M^(n) = d^n M / d mu^n at mu = 0.  Applied right to
+    left: v = eta, then for i = j..1: v = M^{-1} v, v = M^(n_i) v.  Returns the
+    n complex terms (their mean over many vectors estimates the trace)."""
+    eta_e, eta_o = _c128(eta_e), _c128(eta_o)
+    v_e, v_o = eta_e, eta_o
+    for nder in reversed(list(orders)):
+        v_e, v_o, _ = solve_full(L, U, N, m, v_e, v_o, tol=tol)
+        v_e, v_o = apply_M(L, U, N, m, v_e, v_o, nder)
+    n = eta_e.shape[2]
+    return np.array([np.vdot(eta_e[..., k], v_e[..., k]) + np.vdot(eta_o[..., k], v_o[..., k])
+                     for k in range(n)])

@@ -50,6 +50,27 @@ def dslash_matrix(L, U, N):
     return D
 
 
+def dslash_dmu_matrix(L, U, N, nder):
+    """d^n D / d mu^n at mu = 0 as a dense matrix: only the time-direction (mu = 3)
+    terms of eq. (3) survive, the h-step hop weighted by h^n (from exp(h mu))."""
+    L = [int(v) for v in L]
+    V = int(np.prod(L))
+    D = np.zeros((3 * V, 3 * V), dtype=np.complex128)
+    for s in range(V):
+        x = _coords(L, s)
+        rows = slice(3 * s, 3 * s + 3)
+        for h, W, backward in ((1, U, False), (-1, U, True), (3, N, False), (-3, N, True)):
+            y = list(x)
+            y[3] = (y[3] + h) % L[3]
+            t = _site(L, y)
+            w = float(h) ** nder
+            if backward:
+                D[rows, 3 * t:3 * t + 3] -= w * W[3, t].conj().T
+            else:
+                D[rows, 3 * t:3 * t + 3] += w * W[3, s]
+    return D
+
+
 def parity_indices(L, parity):
     """Dense row indices of one parity, ordered by s // 2 (the half-field order)."""
     L = [int(v) for v in L]

@@ -27,6 +27,15 @@
  *   orc_r14_pack /    the 14-real compressed Naik storage of Sec. 1 (Table 1,
  *   orc_r14_unpack    "r14"): rows 0 and 1 plus one complex c with
  *                     row2 = c * conj(row0 x row1), exact for N = s * U(3).
+ *   orc_dslash_chem_eo
+ *                     d^n/dmu^n of the Dslash at quark chemical potential mu,
+ *                     one output parity: the operators dM/dmu of Sec. 1 eq. (2).
+ *                     The paper does not write M(mu) out; the reading is the
+ *                     usual one: a hop of h steps in the time direction carries
+ *                     exp(h mu) (forward 1-hop e^mu, backward e^-mu, Naik e^{+-3mu}),
+ *                     spatial hops carry no mu.  So the n-th derivative weights a
+ *                     temporal h-hop by h^n exp(h mu) and drops spatial hops for
+ *                     n >= 1; n = 0 is D(mu) itself.
  *
  * Layouts: site s = x0 + L0*(x1 + L1*(x2 + L2*x3)); links [4][V][3][3] complex;
  * full fields [V][3][n]; half fields [V/2][3][n] indexed by s/2 within a parity.
@@ -130,6 +139,65 @@ static void dslash_site(const lat_t* t, int n, const zc* U, const zc* N,
 
 static long ident(long s) { return s; }
 static long halve(long s) { return s / 2; }
+
+/* h^n exp(h mu): the n-th mu-derivative of the weight of an h-step temporal hop */
+static double hop_weight(int h, int nder, double mu)
+{
+    double w = exp(h * mu);
+    for (int j = 0; j < nder; ++j) w *= h;
+    return w;
+}
+
+/* One output site of d^n D(mu) / d mu^n (reading above), all n rhs. */
+static void dslash_chem_site(const lat_t* t, int n, const zc* U, const zc* N, const zc* v,
+                             long x, double mu_c, int nder, zc* w)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < n; ++k) w[a * n + k] = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        double wp1, wm1, wp3, wm3;
+        if (mu == 3) {
+            wp1 = hop_weight(+1, nder, mu_c);
+            wm1 = hop_weight(-1, nder, mu_c);
+            wp3 = hop_weight(+3, nder, mu_c);
+            wm3 = hop_weight(-3, nder, mu_c);
+        } else {
+            wp1 = wm1 = wp3 = wm3 = nder == 0 ? 1.0 : 0.0;
+        }
+        long xp1 = hop(t, x, mu, +1), xm1 = hop(t, x, mu, -1);
+        long xp3 = hop(t, x, mu, +3), xm3 = hop(t, x, mu, -3);
+        long ip1 = xp1 / 2, im1 = xm1 / 2, ip3 = xp3 / 2, im3 = xm3 / 2;
+        for (int a = 0; a < 3; ++a) {
+            for (int k = 0; k < n; ++k) {
+                zc acc = 0;
+                for (int b = 0; b < 3; ++b) {
+                    acc += wp1 * link_el(U, t, mu, x, a, b) * v[(ip1 * 3 + b) * n + k];
+                    acc -= wm1 * conj(link_el(U, t, mu, xm1, b, a)) * v[(im1 * 3 + b) * n + k];
+                    acc += wp3 * link_el(N, t, mu, x, a, b) * v[(ip3 * 3 + b) * n + k];
+                    acc -= wm3 * conj(link_el(N, t, mu, xm3, b, a)) * v[(im3 * 3 + b) * n + k];
+                }
+                w[a * n + k] += acc;
+            }
+        }
+    }
+}
+
+int orc_dslash_chem_eo(const int* L, int n, int out_parity, const double* U, const double* N,
+                       double mu_c, int nder, const double* in, double* out)
+{
+    lat_t t;
+    int rc = lat_init(&t, L);
+    if (rc) return rc;
+    if (n < 1 || nder < 0 || (out_parity != 0 && out_parity != 1) || !U || !N || !in || !out)
+        return -1;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < t.V; ++x) {
+        if (parity_of(&t, x) != out_parity) continue;
+        dslash_chem_site(&t, n, (const zc*)U, (const zc*)N, (const zc*)in, x, mu_c, nder,
+                         (zc*)out + (x / 2) * 3 * n);
+    }
+    return 0;
+}
 
 int orc_dslash_full(const int* L, int n, const double* U, const double* N,
                     const double* v, double* w)

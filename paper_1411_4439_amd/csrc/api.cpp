@@ -166,13 +166,38 @@ hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<float>& a, hipStre
 std::mutex g_tune_mu;
 std::map<std::string, Tile> g_tune_cache;
 int g_tune_mode = 0;
-int g_force_nr = 0, g_force_bs = 0, g_force_order = 1;
+int g_force_nr = 0, g_force_bs = 0, g_force_order = 1, g_force_rows = 0;
 
-// Tile order 2 needs tiles that never straddle a time slice.
-bool t_order_ok(const Lat& lat, int G, int bs)
+// Tile order 2 needs tiles that never straddle a time slice; order 3 needs
+// z-chunks of whole planes for each of the 8 XCDs and tiles that divide an x-y
+// plane.
+bool t_order_ok(const Lat& lat, int G, int bs, int order)
 {
-    const long slice_threads = (long)lat.Vh / lat.L[3] * G;
-    return slice_threads % bs == 0;
+    if (order == 2) {
+        const long slice_threads = (long)lat.Vh / lat.L[3] * G;
+        return slice_threads % bs == 0;
+    }
+    if (order == 3) {
+        const int tile_sites = bs / G;
+        const int plane = lat.L[0] * lat.L[1] / 2;
+        return bs % G == 0 && lat.L[2] % 8 == 0 && plane % tile_sites == 0;
+    }
+    return order == 0 || order == 1;
+}
+
+// Block size of the LDS-staged Dslash with R x-rows per tile and G lanes per
+// site, or 0 where that tile is not possible: whole waves, at most
+// kMaxBlockLds threads, tiles that never straddle a plane, staged rows within
+// kMaxStageBytes.
+int staged_block(const Lat& lat, int n, int G, int R, int prec)
+{
+    if (R < 1) return 0;
+    const long bs = (long)R * lat.Lh0 * G;
+    const size_t elt = prec == HISQ_PREC_F64 ? 16 : 8;
+    const size_t lds = (size_t)3 * (R + 6) * lat.Lh0 * n * elt;
+    if (bs % 64 != 0 || bs > kMaxBlockLds || lat.L[1] % R != 0 || lds > (size_t)kMaxStageBytes)
+        return 0;
+    return (int)bs;
 }
 
 Tile default_tile(int n, int prec)
@@ -203,17 +228,20 @@ template <typename T>
 int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& probe, hipStream_t s,
              Tile* out, int epi = EPI_PLAIN, bool cm = true)
 {
-    int mode, fnr, fbs, ford;
+    int mode, fnr, fbs, ford, frows;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         mode = g_tune_mode;
         fnr = g_force_nr;
         fbs = g_force_bs;
         ford = g_force_order;
+        frows = g_force_rows;
     }
     if (mode == 1 && valid_nr(n, fnr)) {
-        if (ford == 2 && !t_order_ok(lat, n / fnr, fbs)) ford = 1;
-        *out = Tile{fnr, fbs, ford};
+        const int sbs = cm ? staged_block(lat, n, n / fnr, frows, prec) : 0;
+        Tile t{fnr, sbs ? sbs : fbs, ford, sbs ? frows : 0};
+        if (!t_order_ok(lat, n / fnr, t.bs, t.remap)) t.remap = 1;
+        *out = t;
         return HISQ_OK;
     }
     if (mode != 0) {
@@ -234,14 +262,24 @@ int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& pro
     HIP_TRY(hipEventCreate(&e1));
     Tile best = default_tile(n, prec);
     float best_ms = 1e30f;
-    const int bss[3] = {64, 128, 256};
+    // candidates: unstaged tiles of 64, 128, 256 threads, then (colour-major
+    // only) LDS-staged tiles of 1..16 rows
+    std::vector<Tile> cand;
     for (int G = 1; G <= 8; G *= 2) {
         if (n % G != 0) continue;
-        const int nr = n / G;
-        for (int bi = 0; bi < 3; ++bi)
-            for (int remap = 0; remap < 3; ++remap) {
-                const Tile c{nr, bss[bi], remap};
-                if (remap == 2 && !t_order_ok(lat, G, bss[bi])) continue;
+        for (int bs : {64, 128, 256}) cand.push_back(Tile{n / G, bs, 0, 0});
+        if (cm)
+            for (int R = 1; R <= 16; ++R) {
+                const int sbs = staged_block(lat, n, G, R, prec);
+                if (sbs) cand.push_back(Tile{n / G, sbs, 0, R});
+            }
+    }
+    for (const Tile& base : cand) {
+        const int G = n / base.nr;
+        for (int remap = 0; remap < 4; ++remap) {
+                Tile c = base;
+                c.remap = remap;
+                if (!t_order_ok(lat, G, c.bs, remap)) continue;
                 if (launch_ds(epi, n, r14, c, probe, s, cm) != hipSuccess) continue;
                 HIP_TRY(hipEventRecord(e0, s));
                 for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, r14, c, probe, s, cm));
@@ -728,6 +766,7 @@ int Engine::finish(CgState* host, hisq_info* infos, double seconds)
             info->block_size = P.size() == 1 ? t.bs : batch_bs;
             info->rhs_per_thread = t.nr;
             info->tile_order = P.size() == 1 ? t.remap : 0;
+            info->stage_rows = P.size() == 1 ? t.rows : 0;
         }
         int maxit = 0;
         for (int k = 0; k < q.n; ++k) {
@@ -1179,7 +1218,7 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
     return E.run(infos);
 }
 
-int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order)
+int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order, int stage_rows)
 {
     if (mode < 0 || mode > 2) return fail(HISQ_EINVAL, "unknown tuning mode %d", mode);
     if (mode == 1) {
@@ -1187,13 +1226,15 @@ int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order
             return fail(HISQ_EINVAL, "rhs_per_thread must be in 1..8");
         if (block_size != 64 && block_size != 128 && block_size != 256)
             return fail(HISQ_EINVAL, "block_size must be 64, 128 or 256");
-        if (tile_order < 0 || tile_order > 2) return fail(HISQ_EINVAL, "tile_order must be 0, 1 or 2");
+        if (tile_order < 0 || tile_order > 3) return fail(HISQ_EINVAL, "tile_order must be 0..3");
+        if (stage_rows < 0 || stage_rows > 64) return fail(HISQ_EINVAL, "stage_rows must be 0..64");
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_mode = mode;
     g_force_nr = rhs_per_thread;
     g_force_bs = block_size;
     g_force_order = mode == 1 ? tile_order : 1;
+    g_force_rows = mode == 1 ? stage_rows : 0;
     return HISQ_OK;
 }
 

@@ -60,7 +60,7 @@ __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, 
 template <typename T, int NRHS, int NR>
 __global__ __launch_bounds__(kMaxBlock) void k_pupdate(const PupdateArgs<T> a)
 {
-    pupdate_tile<T, NRHS, NR>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat.L[3]), gridDim.x,
+    pupdate_tile<T, NRHS, NR>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat, (int)blockDim.x / (NRHS / NR)), gridDim.x,
                               blockIdx.x);
 }
 

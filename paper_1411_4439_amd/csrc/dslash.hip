@@ -154,14 +154,24 @@ __device__ __forceinline__ int neighbour(const Lat& lat, const SiteCoord& sc)
     }
 }
 
+// Pipeline step k -> slot: even steps take the z and t slots, odd steps the x
+// and y slots, hops +1, -1, +3, -3 within each direction.  The LDS-staged
+// kernel reads the x and y neighbours from LDS and overlaps them with the
+// global z and t reads; the unstaged kernel sums the slots in the same order,
+// so the two give bitwise identical results.
+__host__ __device__ constexpr int slot_at(int k)
+{
+    return ((k & 1) ? ((k >> 3) & 1) : 2 + ((k >> 3) & 1)) + 4 * ((k >> 1) & 3);
+}
+
 // acc[c][k] = (D in)_{i}, colour c, rhs g*NR + k, output parity P.
 // Slot s = 4*hop + mu applies matrix s of the parity block to the neighbour
 // reached by hop (+1, -1, +3, -3) in direction mu.  The 16 slots run as a
-// software pipeline: while slot s is multiplied, the neighbour vectors of slot
-// s+1 and the matrices of slots s+1 and s+2 are in flight (links stream from
-// HBM and see the longest latency; neighbour vectors mostly hit L2).  The
-// scheduling barriers keep the compiler from hoisting further loads, which
-// would otherwise exhaust the register file.
+// software pipeline: while one slot is multiplied, the neighbour vectors of
+// the next slot and its matrix are in flight (links stream from HBM and see
+// the longest latency; neighbour vectors mostly hit L2).  The scheduling
+// barriers keep the compiler from hoisting further loads, which would
+// otherwise exhaust the register file.
 template <typename T, int NRHS, int NR, bool R14, bool CM>
 __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
                                             const cplx<T>* __restrict__ lk,
@@ -184,16 +194,135 @@ __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
     constexpr int LD = sizeof(T) == 4 ? HISQ_FP32_LINK_LOOKAHEAD : 1;
     C m[LD + 1][9];
     C v[2][3][NR];
-    load_link<T, R14, 0>(lk, Vh, i, m[0]);
-    if constexpr (LD == 2) load_link<T, R14, 1>(lk, Vh, i, m[1]);
-    load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<0>(lat, sc), g, v[0]);
-    static_for<0, 16>([&](auto S) {
-        constexpr int s = decltype(S)::value;
-        if constexpr (s + LD < 16) load_link<T, R14, s + LD>(lk, Vh, i, m[(s + LD) % (LD + 1)]);
-        if constexpr (s + 1 < 16)
-            load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<s + 1>(lat, sc), g, v[(s + 1) & 1]);
+    load_link<T, R14, slot_at(0)>(lk, Vh, i, m[0]);
+    if constexpr (LD == 2) load_link<T, R14, slot_at(1)>(lk, Vh, i, m[1]);
+    load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(0)>(lat, sc), g, v[0]);
+    static_for<0, 16>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (k + LD < 16)
+            load_link<T, R14, slot_at(k + LD)>(lk, Vh, i, m[(k + LD) % (LD + 1)]);
+        if constexpr (k + 1 < 16)
+            load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(k + 1)>(lat, sc), g, v[(k + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
-        apply_slot<T, NR, R14, s>(m[s % (LD + 1)], v[s & 1], acc);
+        apply_slot<T, NR, R14, slot_at(k)>(m[k % (LD + 1)], v[k & 1], acc);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged form (colour-major fields).  A work-group covers R whole x-rows
+// of one (z, t) plane.  The input rows y0-3 .. y0+R+2 of that plane (periodic
+// in y) are copied to LDS once, laid out [3][R+6][L0/2][n]; the x and y
+// neighbours (8 of the 16 slots) are then read from LDS and only the z and t
+// neighbours and the links come from global memory.
+
+template <typename T, int NRHS>
+__device__ __forceinline__ void stage_rows(const cplx<T>* __restrict__ in, cplx<T>* lds,
+                                           const Lat& lat, int row0, int R)
+{
+    const int Ly = lat.L[1];
+    const int plane = row0 / Ly, y0 = row0 - plane * Ly;
+    const unsigned rows = (unsigned)R + 6;
+    // half-site of staged row j (y0 - 3 + j, periodic; Ly >= 4 > 3)
+    auto row_site = [&](unsigned j) -> size_t {
+        int yy = y0 - 3 + (int)j;
+        yy += yy < 0 ? Ly : 0;
+        yy -= yy >= Ly ? Ly : 0;
+        return (size_t)(plane * Ly + yy) * lat.Lh0;
+    };
+    if constexpr (sizeof(T) == 4) {
+        if ((lat.Lh0 * NRHS) % 2 == 0) {
+            // 16-byte units of two complex numbers
+            const unsigned chunk = (unsigned)(lat.Lh0 * NRHS / 2);
+            const unsigned total = 3u * rows * chunk;
+            const f4* src = reinterpret_cast<const f4*>(in);
+            f4* dst = reinterpret_cast<f4*>(lds);
+            for (unsigned u = threadIdx.x; u < total; u += blockDim.x) {
+                const unsigned cj = u / chunk, off = u - cj * chunk;
+                const unsigned c = cj / rows, j = cj - c * rows;
+                dst[u] = src[((size_t)c * lat.Vh + row_site(j)) * NRHS / 2 + off];
+            }
+            return;
+        }
+    }
+    const unsigned chunk = (unsigned)(lat.Lh0 * NRHS);
+    const unsigned total = 3u * rows * chunk;
+    for (unsigned u = threadIdx.x; u < total; u += blockDim.x) {
+        const unsigned cj = u / chunk, off = u - cj * chunk;
+        const unsigned c = cj / rows, j = cj - c * rows;
+        lds[u] = in[((size_t)c * lat.Vh + row_site(j)) * NRHS + off];
+    }
+}
+
+template <typename T, int NRHS, int NR>
+__device__ __forceinline__ void load_vec_lds(const cplx<T>* lds, int cstride, int site, int g,
+                                             cplx<T> (&v)[3][NR])
+{
+    const cplx<T>* vp = lds + site * NRHS + g * NR;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + b * cstride, v[b]);
+}
+
+// Staged row-local index of the x / y neighbour of slot S (mu = 0 or 1) of the
+// output site in row r of the tile, half-x xh, full x coordinate x.
+template <int S>
+__device__ __forceinline__ int lds_neighbour(const Lat& lat, int r, int xh, int x)
+{
+    constexpr int mu = S & 3;
+    constexpr int hh = S >> 2;
+    constexpr int h = hh == 0 ? 1 : hh == 1 ? -1 : hh == 2 ? 3 : -3;
+    static_assert(mu < 2, "only x and y neighbours are staged");
+    if constexpr (mu == 0) {
+        const int xp = x + wrap_delta(x, h, lat.L[0]);
+        return (r + 3) * lat.Lh0 + (xp >> 1);
+    } else {
+        return (r + 3 + h) * lat.Lh0 + xh;
+    }
+}
+
+// As dslash_site, for the site in row r of an LDS-staged tile.  Issue order
+// follows use order, because a wait for one global read is a wait for every
+// read issued before it: an even (global) step issues the next link, computes,
+// then issues the link after that and the global neighbour of four steps ahead
+// (two global slots of lookahead), and the LDS neighbour of the next step.
+template <typename T, int NRHS, int NR, bool R14>
+__device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, int g, int r,
+                                                const cplx<T>* __restrict__ lk,
+                                                const cplx<T>* __restrict__ in,
+                                                const cplx<T>* lds, int rows,
+                                                cplx<T> (&acc)[3][NR])
+{
+    using C = cplx<T>;
+    const int Vh = lat.Vh;
+    const SiteCoord sc = site_coord(lat, P, i);
+    const int xh = i - sc.row;
+    const int cstride = rows * lat.Lh0 * NRHS;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[c][k] = C{0, 0};
+    C m[2][9];
+    C vg[2][3][NR];
+    C vl[3][NR];
+    load_link<T, R14, slot_at(0)>(lk, Vh, i, m[0]);
+    load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(0)>(lat, sc), g, vg[0]);
+    load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(2)>(lat, sc), g, vg[1]);
+    static_for<0, 16>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        if constexpr (k % 2 == 0) {
+            load_link<T, R14, slot_at(k + 1)>(lk, Vh, i, m[(k + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            apply_slot<T, NR, R14, slot_at(k)>(m[k & 1], vg[(k >> 1) & 1], acc);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (k + 2 < 16) load_link<T, R14, slot_at(k + 2)>(lk, Vh, i, m[k & 1]);
+            if constexpr (k + 4 < 16)
+                load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(k + 4)>(lat, sc), g,
+                                            vg[(k >> 1) & 1]);
+            load_vec_lds<T, NRHS, NR>(lds, cstride,
+                                      lds_neighbour<slot_at(k + 1)>(lat, r, xh, sc.x), g, vl);
+        } else {
+            apply_slot<T, NR, R14, slot_at(k)>(m[k & 1], vl, acc);
+        }
         __builtin_amdgcn_sched_barrier(0);
     });
 }
@@ -255,8 +384,9 @@ __device__ __forceinline__ double norm2c(cplx<T> v)
 // One tile (one work-group's worth of sites) of a half-Dslash with epilogue
 // EPI; `tile` is the tile index, the problem's grid has nblk work-groups and
 // this one is number bid (for the reductions).
-template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM>
-__device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, int nblk, int bid)
+template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM, bool ST = false>
+__device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, int nblk, int bid,
+                                            cplx<T>* lds = nullptr)
 {
     using C = cplx<T>;
     constexpr int G = NRHS / NR;
@@ -290,9 +420,20 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
     const T m4 = (T)a.mass4;
 
     const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
+    if constexpr (ST) {
+        // the tile is `rows` whole x-rows: stage them and their +-3 row halo
+        static_assert(CM, "staging reads colour-major fields");
+        stage_rows<T, NRHS>(a.in, lds, a.lat, tile * a.rows, a.rows);
+        __syncthreads();
+    }
     if (i < a.lat.Vh) {
         C acc[3][NR];
-        dslash_site<T, NRHS, NR, R14, CM>(a.lat, a.parity, i, g, a.links, a.in, acc);
+        if constexpr (ST)
+            dslash_site_lds<T, NRHS, NR, R14>(a.lat, a.parity, i, g,
+                                              ((int)threadIdx.x / G) / a.lat.Lh0, a.links, a.in,
+                                              lds, a.rows + 6, acc);
+        else
+            dslash_site<T, NRHS, NR, R14, CM>(a.lat, a.parity, i, g, a.links, a.in, acc);
         pin_acc(acc);
         using Lay = Layout<NRHS, CM>;
         const int base = Lay::site(i) + g * NR;
@@ -310,9 +451,9 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 C pv[NR], xv[NR], rv[NR];
-                load_rhs<NR>(a.p + base + Lay::colour(c, a.lat.Vh), pv);
-                load_rhs<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
-                load_rhs<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
+                load_rhs<NR, true>(a.p + base + Lay::colour(c, a.lat.Vh), pv);
+                load_rhs<NR, true>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
+                load_rhs<NR, true>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     const C q = C{m4 * pv[k].x - acc[c][k].x, m4 * pv[k].y - acc[c][k].y};
@@ -322,8 +463,8 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
                     }
                     part[k] += norm2c<T>(rv[k]);
                 }
-                store_rhs<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
-                store_rhs<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
+                store_rhs<NR, true>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
+                store_rhs<NR, true>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
             }
             }
         } else if constexpr (EPI == EPI_RESID) {
@@ -362,8 +503,19 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM>
 __global__ __launch_bounds__(kMaxBlock) HISQ_KATTR void k_dslash(const DslashArgs<T> a)
 {
-    dslash_tile<T, NRHS, NR, R14, EPI, CM>(a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat.L[3]), gridDim.x,
-                                       blockIdx.x);
+    const int tile_sites = (int)blockDim.x / (NRHS / NR);
+    dslash_tile<T, NRHS, NR, R14, EPI, CM>(
+        a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat, tile_sites), gridDim.x, blockIdx.x);
+}
+
+template <typename T, int NRHS, int NR, bool R14, int EPI>
+__global__ __launch_bounds__(kMaxBlockLds) void k_dslash_lds(const DslashArgs<T> a)
+{
+    extern __shared__ __align__(16) unsigned char hisq_stage[];
+    const int tile_sites = (int)blockDim.x / (NRHS / NR);
+    dslash_tile<T, NRHS, NR, R14, EPI, true, true>(
+        a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat, tile_sites), gridDim.x, blockIdx.x,
+        reinterpret_cast<cplx<T>*>(hisq_stage));
 }
 
 // Batched form: one launch covers the tiles of every problem of a BatchTable;
@@ -404,6 +556,15 @@ static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s, bool cm)
     const long threads = (long)a.lat.Vh * G;
     a.ntiles = (int)((threads + t.bs - 1) / t.bs);
     a.remap = t.remap;
+    a.rows = t.rows;
+    if (t.rows > 0) {
+        // LDS-staged: colour-major only; the host has checked that a tile is
+        // t.rows whole x-rows of one plane and that the rows fit in LDS
+        if (!cm) return hipErrorInvalidValue;
+        const size_t lds = (size_t)3 * (t.rows + 6) * a.lat.Lh0 * NRHS * sizeof(cplx<T>);
+        hipLaunchKernelGGL((k_dslash_lds<T, NRHS, NR, R14, EPI>), dim3(a.ntiles), dim3(t.bs), lds, s, a);
+        return hipGetLastError();
+    }
     // the solver's kernels exist in colour-major form only; the plain Dslash in both
     if (cm)
         hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI, true>), dim3(a.ntiles), dim3(t.bs), 0, s, a);

@@ -17,15 +17,24 @@ namespace hisq {
 //            outputs at t+-1 and t+-3; in canonical order those run a whole time
 //            slice apart and the site is fetched again for each, in this order
 //            they run back to back and hit L2.  Needs nb = Lt * (tiles per slice).
-__device__ inline int tile_of_block(int b, int nb, int order, int Lt)
+__device__ inline int tile_of_block(int b, int nb, int order, const Lat& lat, int tile_sites)
 {
     if (order == 0 || nb < 8) return b;
     const int j = b & 7, m = b >> 3;
+    if (order == 3) {
+        // XCD j owns the z-chunk [j*zc, (j+1)*zc) of every time slice and walks
+        // it with the (y, x) plane position outermost, then t, then z, so the
+        // +-1 and +-3 neighbours in every direction but the chunk's z faces
+        // are read while they are still in that XCD's L2.
+        const int zc = lat.L[2] >> 3, C = lat.L[0] * lat.L[1] / 2 / tile_sites;
+        const int zl = m % zc, t = (m / zc) % lat.L[3], c = m / (zc * lat.L[3]);
+        return ((t * lat.L[2] + j * zc + zl) * C) + c;
+    }
     const int q = nb >> 3, rem = nb & 7;
     const int c = j * q + (j < rem ? j : rem) + m;  // XCD-contiguous position
     if (order == 1) return c;
-    const int per_slice = nb / Lt;
-    return (c % Lt) * per_slice + c / Lt;
+    const int per_slice = nb / lat.L[3];
+    return (c % lat.L[3]) * per_slice + c / lat.L[3];
 }
 
 __device__ inline double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
@@ -84,7 +93,7 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
 {
     constexpr int G = NRHS / NR;
     static_assert(G == 1 || G == 2 || G == 4 || G == 8, "rhs groups must be a power of two");
-    __shared__ double sred[kMaxBlock / 64][kMaxRhs];
+    __shared__ double sred[kMaxBlockLds / 64][kMaxRhs];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
@@ -172,48 +181,65 @@ struct Layout {
 };
 
 // Loads and stores of NR consecutive complex numbers (rhs of one colour).
-template <int NR>
+// NT: streamed data, read or written once per launch; the non-temporal hint
+// keeps it from evicting the gathered neighbour field from L2.
+template <bool NT, typename V>
+__device__ __forceinline__ V ld(const V* p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void st(V* p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <int NR, bool NT = false>
 __device__ __forceinline__ void load_rhs(const f2* __restrict__ p, f2 (&v)[NR])
 {
     if constexpr (NR % 2 == 0) {
         const f4* q = reinterpret_cast<const f4*>(p);
 #pragma unroll
         for (int k = 0; k < NR / 2; ++k) {
-            f4 w = q[k];
+            f4 w = ld<NT>(q + k);
             v[2 * k] = f2{w.x, w.y};
             v[2 * k + 1] = f2{w.z, w.w};
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) v[k] = p[k];
+        for (int k = 0; k < NR; ++k) v[k] = ld<NT>(p + k);
     }
 }
 
-template <int NR>
+template <int NR, bool NT = false>
 __device__ __forceinline__ void load_rhs(const d2* __restrict__ p, d2 (&v)[NR])
 {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) v[k] = p[k];
+    for (int k = 0; k < NR; ++k) v[k] = ld<NT>(p + k);
 }
 
-template <int NR>
+template <int NR, bool NT = false>
 __device__ __forceinline__ void store_rhs(f2* __restrict__ p, const f2 (&v)[NR])
 {
     if constexpr (NR % 2 == 0) {
         f4* q = reinterpret_cast<f4*>(p);
 #pragma unroll
-        for (int k = 0; k < NR / 2; ++k) q[k] = f4{v[2 * k].x, v[2 * k].y, v[2 * k + 1].x, v[2 * k + 1].y};
+        for (int k = 0; k < NR / 2; ++k)
+            st<NT>(q + k, f4{v[2 * k].x, v[2 * k].y, v[2 * k + 1].x, v[2 * k + 1].y});
     } else {
 #pragma unroll
-        for (int k = 0; k < NR; ++k) p[k] = v[k];
+        for (int k = 0; k < NR; ++k) st<NT>(p + k, v[k]);
     }
 }
 
-template <int NR>
+template <int NR, bool NT = false>
 __device__ __forceinline__ void store_rhs(d2* __restrict__ p, const d2 (&v)[NR])
 {
 #pragma unroll
-    for (int k = 0; k < NR; ++k) p[k] = v[k];
+    for (int k = 0; k < NR; ++k) st<NT>(p + k, v[k]);
 }
 
 }  // namespace hisq

@@ -51,6 +51,10 @@ constexpr int kMaxRhs = HISQ_MAX_RHS;
 constexpr size_t kLinkHeaderBytes = 256;
 constexpr uint32_t kLinkMagic = 0x51534948u;  // "HISQ"
 constexpr int kMaxBlock = 256;
+// LDS-staged Dslash: up to 512 threads per work-group, up to 64 KB of staged
+// neighbour rows.
+constexpr int kMaxBlockLds = 512;
+constexpr int kMaxStageBytes = 64 * 1024;
 constexpr float kR14Tolerance = 1e-6f;
 
 struct LinkHeader {
@@ -139,6 +143,7 @@ struct DslashArgs {
     uint32_t* cnt;  // reduction counters (zero between launches)
     int ntiles;
     int remap;
+    int rows;  // LDS-staged x-rows per tile (0: unstaged)
 };
 
 template <typename T>
@@ -179,6 +184,7 @@ struct Tile {
     int nr;
     int bs;
     int remap;
+    int rows = 0;  // > 0: LDS-staged Dslash, the work-group covers `rows` x-rows
 };
 
 // Reduction scratch for a grid of up to `blocks` work-groups.

@@ -50,6 +50,7 @@ class Info(ctypes.Structure):
                 ("reliable_updates", ctypes.c_int32), ("polls", ctypes.c_int32),
                 ("total_iters", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("rhs_per_thread", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("stage_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seconds", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int32 * 4)]
 
@@ -61,6 +62,7 @@ class Info(ctypes.Structure):
             "reliable_updates": self.reliable_updates, "polls": self.polls,
             "total_iters": self.total_iters, "block_size": self.block_size,
             "rhs_per_thread": self.rhs_per_thread, "tile_order": self.tile_order,
+            "stage_rows": self.stage_rows,
             "seconds": self.seconds,
             "kernel_ms": list(self.kernel_ms), "kernel_launches": list(self.kernel_launches),
         }
@@ -92,7 +94,8 @@ _sig = {
     "hisq_cg_solve_batched": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Problem),
                                              ctypes.POINTER(Params), _P, ctypes.c_size_t,
                                              ctypes.POINTER(Info), _P]),
-    "hisq_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "hisq_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int]),
     "hisq_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -216,8 +219,8 @@ def hisq_cg_solve_batched(problems, params, ws, stream=None):
     return _check(rc, "hisq_cg_solve_batched"), list(infos)
 
 
-def hisq_set_tuning(mode, rhs_per_thread=0, block_size=0, tile_order=1):
-    return _check(_lib.hisq_set_tuning(mode, rhs_per_thread, block_size, tile_order),
+def hisq_set_tuning(mode, rhs_per_thread=0, block_size=0, tile_order=1, stage_rows=0):
+    return _check(_lib.hisq_set_tuning(mode, rhs_per_thread, block_size, tile_order, stage_rows),
                   "hisq_set_tuning")
 
 

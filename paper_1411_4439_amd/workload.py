@@ -157,6 +157,23 @@ def random_su3(count: int, seed: int) -> np.ndarray:
     return Q / (det ** (1.0 / 3.0))[:, None, None]
 
 
+def make_noise(L: Sequence[int], n: int, seed: int, kind: str = "z2") -> tuple[np.ndarray, np.ndarray]:
+    """Random vectors for the trace estimator of eq. (2), split into the even and
+    odd half fields ([V/2][3][n] complex128 each): "z2" draws every component
+    from {+1, -1}, "gauss" from a unit complex Gaussian."""
+    Vh = half_volume(L)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kind == "z2":
+        f = 1.0 - 2.0 * rng.integers(0, 2, size=(2, Vh, 3, n))
+        f = f.astype(np.complex128)
+    elif kind == "gauss":
+        g = rng.standard_normal((2, Vh, 3, n, 2)) / np.sqrt(2.0)
+        f = g[..., 0] + 1j * g[..., 1]
+    else:
+        raise ValueError("kind must be 'z2' or 'gauss'")
+    return np.ascontiguousarray(f[0]), np.ascontiguousarray(f[1])
+
+
 def plane_wave(L: Sequence[int], k: Sequence[int], xi: Sequence[complex]) -> np.ndarray:
     """Full-lattice field e^{i p.x} xi with p_mu = 2 pi k_mu / L_mu, shape (V, 3, 1)."""
     c = _coords(L)

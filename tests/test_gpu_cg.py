@@ -208,3 +208,26 @@ def test_headline_mixed_8rhs_true_residual():
         res = oracle.residual(L, U, N, m, b, host(x))
         say("oracle true residual", res)
         assert res.max() <= 1e-10
+
+
+def test_lds_staged_solve_matches_unstaged():
+    """A mixed-precision solve forced onto LDS-staged Dslash tiles reports the
+    staged shape and returns the same bits as the unstaged tiles (the staged
+    kernel sums the 16 slots in the same order)."""
+    H = gpu_lib()
+    L, m, n = (16, 16, 16, 4), 0.02, 8
+    U, N, links, b = _setup(H, L, 0.3, 61, n, 62)
+    bd = dev(b)
+    try:
+        H.hisq_set_tuning(1, 4, 64, 3, 0)
+        x0, s0, i0 = H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        H.hisq_set_tuning(1, 4, 64, 3, 4)
+        x1, s1, i1 = H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+    finally:
+        H.hisq_set_tuning(0)
+    say(i0["stage_rows"], i1["stage_rows"], i1["block_size"], i1["iters"])
+    assert s0 == s1 == H.HISQ_OK
+    assert i0["stage_rows"] == 0 and i1["stage_rows"] == 4 and i1["block_size"] == 4 * 8 * 2
+    assert np.array_equal(host(x0), host(x1))
+    res = oracle.residual(L, U, N, m, b, host(x1))
+    assert res.max() <= 1e-10

@@ -61,7 +61,7 @@ def test_dslash_f64_all_tiles(L, n):
         want = oracle.dslash_eo(L, U, N, v, parity)
         outs = []
         for nr in _tiles(n):
-            for bs, order in ((64, 0), (64, 2), (256, 1), (256, 2)):
+            for bs, order in ((64, 0), (64, 2), (256, 1), (256, 2), (64, 3), (256, 3)):
                 for lay in (H.LAYOUT_SITE, H.LAYOUT_COLOUR):
                     say("f64", L, n, parity, nr, bs, order, lay)
                     H.hisq_set_tuning(1, nr, bs, order)
@@ -85,7 +85,7 @@ def test_dslash_f32_all_tiles(L, n, naik):
         v = _source(L, n, 200 + n + parity).astype(np.complex64)
         want = oracle.dslash_eo(L, U, N, v.astype(np.complex128), parity)
         for nr in _tiles(n):
-            for bs, order, lay in ((64, 2, 0), (128, 1, 0), (64, 2, 1), (128, 1, 1)):
+            for bs, order, lay in ((64, 2, 0), (128, 1, 0), (64, 2, 1), (128, 1, 1), (128, 3, 1)):
                 say("f32", naik, L, n, parity, nr, bs, order, lay)
                 H.hisq_set_tuning(1, nr, bs, order)
                 got = _apply(H, links, parity, v, H.PREC_F32, nk, lay).astype(np.complex128)
@@ -168,3 +168,53 @@ def test_dslash_headline_lattice_sampled_sites():
             g = _apply(H, links, 1, v32, H.PREC_F32, nk, lay).astype(np.complex128)
             assert rel_l2_per_rhs(g[sites // 2], want) <= 1e-6
             assert rel_l2_per_rhs(g, host(ref64)) <= 1e-6
+
+
+def _staged_block(L, n, G, R, prec):
+    """The library's rule for an LDS-staged tile (whole waves, <= 512 threads,
+    R | L1, staged rows <= 64 KB); 0 where the tile is not possible."""
+    Lh0 = L[0] // 2
+    bs = R * Lh0 * G
+    lds = 3 * (R + 6) * Lh0 * n * (16 if prec == 0 else 8)
+    ok = bs % 64 == 0 and bs <= 512 and L[1] % R == 0 and lds <= 64 * 1024
+    return bs if ok else 0
+
+
+STAGED_LATTICES = [(16, 16, 16, 4), (8, 8, 8, 4), (4, 4, 4, 4), (32, 8, 8, 6)]
+
+
+@pytest.mark.parametrize("L", STAGED_LATTICES)
+@pytest.mark.parametrize("n", [1, 2, 4, 8])
+def test_dslash_lds_staged_tiles(L, n):
+    """LDS-staged Dslash (x and y neighbours from staged rows, periodic in y,
+    rows wrapping onto themselves where L1 < rows + 6) in every valid tile and
+    tile order, FP64 / FP32 / r14, bitwise equal to the unstaged kernel of the
+    same precision (same per-site summation order)."""
+    if not any(_staged_block(L, n, G, R, p) for G in (1, 2, 4, 8) if n % G == 0
+               for R in range(1, 17) for p in (0, 1)):
+        pytest.skip("no staged tile of whole waves fits this lattice and bundle")
+    H = gpu_lib()
+    U, N, links = _links(H, L)
+    ran = 0
+    for prec, nk, tol in ((H.PREC_F64, H.NAIK_FULL, 1e-13), (H.PREC_F32, H.NAIK_FULL, 1e-6),
+                          (H.PREC_F32, H.NAIK_R14, 1e-6)):
+        for parity in (0, 1):
+            v = _source(L, n, 500 + n + parity)
+            if prec == H.PREC_F32:
+                v = v.astype(np.complex64)
+            want = oracle.dslash_eo(L, U, N, v.astype(np.complex128), parity)
+            for nr in _tiles(n):
+                G = n // nr
+                H.hisq_set_tuning(1, nr, 64, 1, 0)
+                plain = _apply(H, links, parity, v, prec, nk, H.LAYOUT_COLOUR)
+                for R in range(1, 17):
+                    if not _staged_block(L, n, G, R, prec):
+                        continue
+                    for order in (0, 1, 3):
+                        say("staged", L, n, prec, nk, parity, nr, R, order)
+                        H.hisq_set_tuning(1, nr, 64, order, R)
+                        got = _apply(H, links, parity, v, prec, nk, H.LAYOUT_COLOUR)
+                        assert rel_l2_per_rhs(got.astype(np.complex128), want) <= tol, (nr, R, order)
+                        assert np.array_equal(got, plain), (nr, R, order)
+                        ran += 1
+    assert ran > 0
