@@ -70,6 +70,8 @@ extern "C" {
 
 #define HISQ_MAX_RHS 8
 #define HISQ_MAX_PROBLEMS 16
+#define HISQ_MAX_DERIVATIVE 8   /* highest mu-derivative order of hisq_dslash_dmu     */
+#define HISQ_MAX_INSERTIONS 8   /* operator insertions per hisq_trace_estimate term   */
 
 enum hisq_prec { HISQ_PREC_F64 = 0, HISQ_PREC_F32 = 1 };
 enum hisq_naik { HISQ_NAIK_FULL = 0, HISQ_NAIK_R14 = 1 };
@@ -154,6 +156,10 @@ size_t hisq_backward_workspace_bytes(const hisq_geom* g, int nrhs, int mode);
 /* Workspace bytes for hisq_cg_solve_batched over nprob problems. */
 size_t hisq_batched_workspace_bytes(int nprob, const hisq_problem* probs, int mode);
 
+/* Workspace bytes for hisq_solve_full and hisq_trace_estimate. */
+size_t hisq_full_workspace_bytes(const hisq_geom* g, int nrhs, int mode);
+size_t hisq_trace_workspace_bytes(const hisq_geom* g, int nrhs, int mode);
+
 /*
  * Pack canonical links U, N ([4][V][3][3] complex128, device) into `packed`
  * (device, hisq_links_bytes(g, prec, naik) bytes) for the Dslash of eq. (3).
@@ -216,6 +222,50 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
  */
 int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_params* p, void* ws,
                           size_t ws_bytes, hisq_info* infos, void* stream);
+
+/*
+ * out = d^nder D / d mu^nder in, at mu = 0, from the fields of parity
+ * 1-out_parity to those of parity out_parity: the derivative operators of the
+ * trace formula Sec. 1 eq. (2).  The paper does not write M(mu) out; this
+ * library reads it as the usual one: a temporal hop of h steps (h = +-1 for U,
+ * +-3 for N) carries exp(h mu), spatial hops carry none.  So for nder >= 1 only
+ * the time-direction terms of eq. (3) remain, weighted by h^nder; nder = 0 is
+ * the Dslash itself.  links64: packed FP64/FULL links.  in, out: site-major
+ * [Vh][3][nrhs] complex128.  0 <= nder <= HISQ_MAX_DERIVATIVE.  Asynchronous.
+ */
+int hisq_dslash_dmu(const hisq_geom* g, int out_parity, int nrhs, int nder, const void* links64,
+                    const double* in, double* out, void* stream);
+
+/*
+ * Solve M x = b on the full lattice, M = 2m + D (the reading of the fermion
+ * matrix; Sec. 1 eq. (3) gives D), through the even-odd reduction:
+ * (4m^2 - D_eo D_oe) x_e = 2m b_e - D_eo b_o by the CG of hisq_cg_solve (same
+ * params, start vector zero), then x_o = (b_o - D_oe x_e) / (2m).
+ * b_e, b_o, x_e, x_o: site-major [Vh][3][nrhs] complex128 device buffers.
+ * mass must be finite and nonzero.  info and the return value are those of the
+ * even solve.  Blocks until done.
+ */
+int hisq_solve_full(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                    const void* links64, const void* links32, const double* b_e, const double* b_o,
+                    double* x_e, double* x_o, void* ws, size_t ws_bytes, hisq_info* info,
+                    void* stream);
+
+/*
+ * One bundle of terms of the stochastic trace estimator, Sec. 1 eq. (2):
+ *   est_k = eta_k^dag M^(n_1) M^-1 M^(n_2) M^-1 ... M^(n_j) M^-1 eta_k
+ * for orders = (n_1 .. n_j) (host array, j = ninsert), M^(n) = d^n M / d mu^n
+ * at mu = 0 (hisq_dslash_dmu; n = 0 is M).  Evaluated right to left with
+ * hisq_solve_full for each M^-1.  eta_e, eta_o: the caller's noise vectors
+ * (site-major [Vh][3][nrhs] complex128; the library draws no random numbers).
+ * est: device, [nrhs][2] doubles (re, im).  The mean of est_k over many
+ * vectors estimates the trace.  info: total iterations, reliable updates and
+ * seconds summed over the j solves; the rest from the last solve.  Returns the
+ * worst solve status, or < 0.  Blocks until done.
+ */
+int hisq_trace_estimate(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                        const void* links64, const void* links32, int ninsert, const int* orders,
+                        const double* eta_e, const double* eta_o, double* est, void* ws,
+                        size_t ws_bytes, hisq_info* info, void* stream);
 
 /*
  * Autotuner control (process-wide).  mode 0: time the candidate tiles on first

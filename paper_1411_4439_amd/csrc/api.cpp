@@ -89,9 +89,19 @@ struct Ws {
     d2* y = nullptr;  // backward: adjoint solution, D_oe x, D_oe y
     d2* tx = nullptr;
     d2* sy = nullptr;
+    d2* bp = nullptr;  // full solve: reduced source 2m b_e - D_eo b_o, a Dslash output
+    d2* fo = nullptr;
+    d2* ve = nullptr;  // trace estimator: M^(n) applied (even, odd), M^-1 applied
+    d2* vo = nullptr;
+    d2* xe = nullptr;
+    d2* xo = nullptr;
+    double* dot = nullptr;  // per-work-group partials of the final dot products
 };
 
-size_t ws_layout(const Lat& lat, int n, int mode, bool backward, char* base, Ws* w)
+// What a workspace serves: the extra regions beyond the solver's own.
+enum WsKind { WS_SOLVE = 0, WS_BACKWARD = 1, WS_FULL = 2, WS_TRACE = 3 };
+
+size_t ws_layout(const Lat& lat, int n, int mode, int kind, char* base, Ws* w)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
@@ -118,10 +128,21 @@ size_t ws_layout(const Lat& lat, int n, int mode, bool backward, char* base, Ws*
         w->t32 = (f2*)take(f32);
         w->x32 = (f2*)take(f32);
     }
-    if (backward) {
+    if (kind == WS_BACKWARD) {
         w->y = (d2*)take(f64);
         w->tx = (d2*)take(f64);
         w->sy = (d2*)take(f64);
+    }
+    if (kind == WS_FULL || kind == WS_TRACE) {
+        w->bp = (d2*)take(f64);
+        w->fo = (d2*)take(f64);
+    }
+    if (kind == WS_TRACE) {
+        w->ve = (d2*)take(f64);
+        w->vo = (d2*)take(f64);
+        w->xe = (d2*)take(f64);
+        w->xo = (d2*)take(f64);
+        w->dot = (double*)take((cdot_scratch_doubles(lat.Vh, n) + 2 * kMaxRhs) * sizeof(double));
     }
     return off;
 }
@@ -930,6 +951,97 @@ int solve_impl(double mass, int nrhs, const hisq_params* p, const void* links64,
     return E.run(info);
 }
 
+// x = M^{-1} b on the full lattice, M = 2m + D, through the even-odd
+// reduction: (4m^2 - D_eo D_oe) x_e = 2m b_e - D_eo b_o, then
+// x_o = (b_o - D_oe x_e) / (2m).  Caller's site-major FP64 fields.
+int full_impl(double mass, int n, const hisq_params* p, const void* links64, const void* links32,
+              const d2* b_e, const d2* b_o, d2* x_e, d2* x_o, const Ws& w, hisq_info* info,
+              hipStream_t s, const Lat& lat)
+{
+    const size_t nc = (size_t)lat.Vh * 3 * n;
+    const Tile t = default_tile(n, HISQ_PREC_F64);
+    DslashArgs<double> a{};
+    a.lat = lat;
+    a.parity = 0;
+    a.links = link_block<double>(links64, lat.Vh, false, 0);
+    a.in = b_o;
+    a.out = w.fo;
+    HIP_TRY(launch_ds(EPI_PLAIN, n, false, t, a, s, false));
+    HIP_TRY(launch_axpby(b_e, w.fo, w.bp, nc, 2.0 * mass, -1.0, s));
+    hisq_params q = *p;
+    q.use_x0 = 0;
+    const int st = solve_impl(mass, n, &q, links64, links32, reinterpret_cast<const double*>(w.bp),
+                              reinterpret_cast<double*>(x_e), w, info, s, lat);
+    if (st < 0) return st;
+    a.parity = 1;
+    a.links = link_block<double>(links64, lat.Vh, false, 1);
+    a.in = x_e;
+    a.out = w.fo;
+    HIP_TRY(launch_ds(EPI_PLAIN, n, false, t, a, s, false));
+    HIP_TRY(launch_axpby(b_o, w.fo, x_o, nc, 1.0 / (2.0 * mass), -1.0 / (2.0 * mass), s));
+    return st;
+}
+
+// (y_e, y_o) = d^nder M / d mu^nder (x_e, x_o) at mu = 0; nder = 0 is M itself.
+int apply_dM(double mass, int n, int nder, const void* links64, const d2* x_e, const d2* x_o,
+             d2* y_e, d2* y_o, const Ws& w, hipStream_t s, const Lat& lat)
+{
+    const size_t nc = (size_t)lat.Vh * 3 * n;
+    if (nder > 0) {
+        HIP_TRY(launch_dslash_dmu(lat, 0, n, nder, link_block<double>(links64, lat.Vh, false, 0), x_o,
+                                  y_e, s));
+        HIP_TRY(launch_dslash_dmu(lat, 1, n, nder, link_block<double>(links64, lat.Vh, false, 1), x_e,
+                                  y_o, s));
+        return HISQ_OK;
+    }
+    const Tile t = default_tile(n, HISQ_PREC_F64);
+    DslashArgs<double> a{};
+    a.lat = lat;
+    for (int par = 0; par < 2; ++par) {
+        a.parity = par;
+        a.links = link_block<double>(links64, lat.Vh, false, par);
+        a.in = par == 0 ? x_o : x_e;
+        a.out = w.fo;
+        HIP_TRY(launch_ds(EPI_PLAIN, n, false, t, a, s, false));
+        HIP_TRY(launch_axpby(par == 0 ? x_e : x_o, w.fo, par == 0 ? y_e : y_o, nc, 2.0 * mass, 1.0, s));
+    }
+    return HISQ_OK;
+}
+
+// Per-vector terms of the trace estimator of eq. (2): for orders (n_1..n_j),
+// v = eta, then for i = j..1: v = M^-1 v, v = M^(n_i) v; est_k = eta_k^dag v_k.
+int trace_impl(double mass, int n, const hisq_params* p, const void* links64, const void* links32,
+               int nins, const int* orders, const d2* eta_e, const d2* eta_o, double* est,
+               const Ws& w, hisq_info* info, hipStream_t s, const Lat& lat)
+{
+    const d2* ve = eta_e;
+    const d2* vo = eta_o;
+    int worst = HISQ_OK, total_iters = 0, updates = 0;
+    double secs = 0.0;
+    for (int j = nins - 1; j >= 0; --j) {
+        const int st = full_impl(mass, n, p, links64, links32, ve, vo, w.xe, w.xo, w, info, s, lat);
+        if (st < 0) return st;
+        worst = std::max(worst, st);
+        if (info) {
+            total_iters += info->total_iters;
+            updates += info->reliable_updates;
+            secs += info->seconds;
+        }
+        int rc = apply_dM(mass, n, orders[j], links64, w.xe, w.xo, w.ve, w.vo, w, s, lat);
+        if (rc) return rc;
+        ve = w.ve;
+        vo = w.vo;
+    }
+    HIP_TRY(launch_cdot(eta_e, w.ve, eta_o, w.vo, lat.Vh, n, w.dot, est, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->total_iters = total_iters;
+        info->reliable_updates = updates;
+        info->seconds = secs;
+    }
+    return worst;
+}
+
 // Batched workspace: the states of all problems side by side, the batch
 // table, then each problem's own regions.
 size_t batched_layout(int nprob, const hisq_problem* probs, int mode, char* base,
@@ -947,9 +1059,9 @@ size_t batched_layout(int nprob, const hisq_problem* probs, int mode, char* base
     for (int j = 0; j < nprob; ++j) {
         const Lat lat = make_lat(probs[j].geom);
         Ws w;
-        const size_t need = ws_layout(lat, probs[j].nrhs, mode, false, nullptr, &w);
+        const size_t need = ws_layout(lat, probs[j].nrhs, mode, WS_SOLVE, nullptr, &w);
         char* region = take(need);
-        ws_layout(lat, probs[j].nrhs, mode, false, region, &w);
+        ws_layout(lat, probs[j].nrhs, mode, WS_SOLVE, region, &w);
         w.st = base ? *states + j : nullptr;
         (*ws)[j] = w;
     }
@@ -1015,7 +1127,7 @@ size_t hisq_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
     if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return 0;
     if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
     Ws w;
-    return ws_layout(lat, nrhs, mode, false, nullptr, &w);
+    return ws_layout(lat, nrhs, mode, WS_SOLVE, nullptr, &w);
 }
 
 size_t hisq_backward_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
@@ -1025,7 +1137,27 @@ size_t hisq_backward_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
     if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return 0;
     if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
     Ws w;
-    return ws_layout(lat, nrhs, mode, true, nullptr, &w);
+    return ws_layout(lat, nrhs, mode, WS_BACKWARD, nullptr, &w);
+}
+
+size_t hisq_full_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
+{
+    Lat lat;
+    if (check_geom(g, &lat)) return 0;
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return 0;
+    if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
+    Ws w;
+    return ws_layout(lat, nrhs, mode, WS_FULL, nullptr, &w);
+}
+
+size_t hisq_trace_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
+{
+    Lat lat;
+    if (check_geom(g, &lat)) return 0;
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return 0;
+    if (mode != HISQ_MODE_FP64 && mode != HISQ_MODE_MIXED) return 0;
+    Ws w;
+    return ws_layout(lat, nrhs, mode, WS_TRACE, nullptr, &w);
 }
 
 int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int prec, int naik,
@@ -1112,10 +1244,10 @@ int hisq_cg_solve(const hisq_geom* g, double mass, int nrhs, const hisq_params* 
         return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
     if (!std::isfinite(mass)) return fail(HISQ_EINVAL, "mass must be finite");
     Ws w;
-    const size_t need = ws_layout(lat, nrhs, p->mode, false, nullptr, &w);
+    const size_t need = ws_layout(lat, nrhs, p->mode, WS_SOLVE, nullptr, &w);
     if (ws_bytes < need)
         return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
-    ws_layout(lat, nrhs, p->mode, false, reinterpret_cast<char*>(ws), &w);
+    ws_layout(lat, nrhs, p->mode, WS_SOLVE, reinterpret_cast<char*>(ws), &w);
     return solve_impl(mass, nrhs, p, links64, links32, b_e, x_e, w, info, stream, lat);
 }
 
@@ -1135,10 +1267,10 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     if (p->mode == HISQ_MODE_MIXED && !links32)
         return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
     Ws w;
-    const size_t need = ws_layout(lat, nrhs, p->mode, true, nullptr, &w);
+    const size_t need = ws_layout(lat, nrhs, p->mode, WS_BACKWARD, nullptr, &w);
     if (ws_bytes < need)
         return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
-    ws_layout(lat, nrhs, p->mode, true, reinterpret_cast<char*>(ws), &w);
+    ws_layout(lat, nrhs, p->mode, WS_BACKWARD, reinterpret_cast<char*>(ws), &w);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     d2* y = grad_b ? reinterpret_cast<d2*>(grad_b) : w.y;
     // adjoint solve: A is Hermitian, so A y = grad_x uses the same operator
@@ -1165,6 +1297,99 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
                          w.red, w.cnt, s));
     HIP_TRY(hipStreamSynchronize(s));
     return st;
+}
+
+int hisq_dslash_dmu(const hisq_geom* g, int out_parity, int nrhs, int nder, const void* links64,
+                    const double* in, double* out, void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_geom(g, &lat);
+    if (rc) return rc;
+    if (!links64 || !in || !out) return fail(HISQ_EINVAL, "NULL pointer");
+    if (out_parity != 0 && out_parity != 1) return fail(HISQ_EINVAL, "out_parity must be 0 or 1");
+    if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", nrhs);
+    if (nder < 0 || nder > HISQ_MAX_DERIVATIVE)
+        return fail(HISQ_EINVAL, "nder = %d outside 0..%d", nder, HISQ_MAX_DERIVATIVE);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const d2* vin = reinterpret_cast<const d2*>(in);
+    d2* vout = reinterpret_cast<d2*>(out);
+    const d2* lk = link_block<double>(links64, lat.Vh, false, out_parity);
+    if (nder > 0) {
+        HIP_TRY(launch_dslash_dmu(lat, out_parity, nrhs, nder, lk, vin, vout, s));
+        return HISQ_OK;
+    }
+    DslashArgs<double> a{};
+    a.lat = lat;
+    a.parity = out_parity;
+    a.links = lk;
+    a.in = vin;
+    a.out = vout;
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, default_tile(nrhs, HISQ_PREC_F64), a, s, false));
+    return HISQ_OK;
+}
+
+static int check_full_args(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                           const void* links64, const void* links32, Lat* lat)
+{
+    int rc = check_geom(g, lat);
+    if (rc) return rc;
+    if ((rc = check_params(p, nrhs))) return rc;
+    if (!links64) return fail(HISQ_EINVAL, "NULL pointer");
+    if (p->mode == HISQ_MODE_MIXED && !links32)
+        return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
+    if (!std::isfinite(mass) || mass == 0.0)
+        return fail(HISQ_EINVAL, "mass must be finite and nonzero (x_o = (b_o - D_oe x_e) / 2m)");
+    return HISQ_OK;
+}
+
+int hisq_solve_full(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                    const void* links64, const void* links32, const double* b_e, const double* b_o,
+                    double* x_e, double* x_o, void* ws, size_t ws_bytes, hisq_info* info,
+                    void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_full_args(g, mass, nrhs, p, links64, links32, &lat);
+    if (rc) return rc;
+    if (!b_e || !b_o || !x_e || !x_o || !ws) return fail(HISQ_EINVAL, "NULL pointer");
+    Ws w;
+    const size_t need = ws_layout(lat, nrhs, p->mode, WS_FULL, nullptr, &w);
+    if (ws_bytes < need)
+        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    ws_layout(lat, nrhs, p->mode, WS_FULL, reinterpret_cast<char*>(ws), &w);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    rc = full_impl(mass, nrhs, p, links64, links32, reinterpret_cast<const d2*>(b_e),
+                   reinterpret_cast<const d2*>(b_o), reinterpret_cast<d2*>(x_e),
+                   reinterpret_cast<d2*>(x_o), w, info, s, lat);
+    if (rc < 0) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return rc;
+}
+
+int hisq_trace_estimate(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                        const void* links64, const void* links32, int ninsert, const int* orders,
+                        const double* eta_e, const double* eta_o, double* est, void* ws,
+                        size_t ws_bytes, hisq_info* info, void* stream)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_full_args(g, mass, nrhs, p, links64, links32, &lat);
+    if (rc) return rc;
+    if (!eta_e || !eta_o || !est || !ws || !orders) return fail(HISQ_EINVAL, "NULL pointer");
+    if (ninsert < 1 || ninsert > HISQ_MAX_INSERTIONS)
+        return fail(HISQ_EINVAL, "ninsert = %d outside 1..%d", ninsert, HISQ_MAX_INSERTIONS);
+    for (int j = 0; j < ninsert; ++j)
+        if (orders[j] < 0 || orders[j] > HISQ_MAX_DERIVATIVE)
+            return fail(HISQ_EINVAL, "orders[%d] = %d outside 0..%d", j, orders[j], HISQ_MAX_DERIVATIVE);
+    Ws w;
+    const size_t need = ws_layout(lat, nrhs, p->mode, WS_TRACE, nullptr, &w);
+    if (ws_bytes < need)
+        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    ws_layout(lat, nrhs, p->mode, WS_TRACE, reinterpret_cast<char*>(ws), &w);
+    return trace_impl(mass, nrhs, p, links64, links32, ninsert, orders,
+                      reinterpret_cast<const d2*>(eta_e), reinterpret_cast<const d2*>(eta_o), est, w,
+                      info, reinterpret_cast<hipStream_t>(stream), lat);
 }
 
 size_t hisq_batched_workspace_bytes(int nprob, const hisq_problem* probs, int mode)

@@ -465,4 +465,107 @@ hipError_t launch_redot(const d2* y, const d2* x, int Vh, int nrhs, double scale
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// out = alpha a + beta b over n complex numbers (real scalars).
+__global__ void k_axpby(const d2* __restrict__ a, const d2* __restrict__ b, d2* __restrict__ out,
+                        size_t n, double alpha, double beta)
+{
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const d2 x = a[e], y = b[e];
+        out[e] = d2{alpha * x.x + beta * y.x, alpha * x.y + beta * y.y};
+    }
+}
+
+hipError_t launch_axpby(const d2* a, const d2* b, d2* out, size_t n, double alpha, double beta,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, b, out, n, alpha, beta);
+    return hipGetLastError();
+}
+
+// Per-rhs complex dot products sum_i conj(a_i) b_i over an even and an odd half
+// field (site-major, n rhs), in a fixed order: stage 1 writes one partial per
+// work-group and rhs (re, im), stage 2 sums the partials in work-group order.
+template <int NRHS>
+__global__ __launch_bounds__(256) void k_cdot_partial(const d2* __restrict__ ae, const d2* __restrict__ be,
+                                                      const d2* __restrict__ ao, const d2* __restrict__ bo,
+                                                      int Vh, double* __restrict__ part)
+{
+    __shared__ double sh[4][2 * NRHS];
+    double re[NRHS], im[NRHS];
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) re[k] = im[k] = 0.0;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < 2 * Vh) {
+        const bool even = j < Vh;
+        const size_t i = even ? j : j - Vh;
+        const d2* a = even ? ae : ao;
+        const d2* b = even ? be : bo;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                const d2 x = a[(i * 3 + c) * NRHS + k], y = b[(i * 3 + c) * NRHS + k];
+                re[k] += x.x * y.x + x.y * y.y;
+                im[k] += x.x * y.y - x.y * y.x;
+            }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NRHS; ++k) {
+        re[k] = wave_sum(re[k]);
+        im[k] = wave_sum(im[k]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) {
+            sh[wave][2 * k] = re[k];
+            sh[wave][2 * k + 1] = im[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NRHS) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][threadIdx.x];
+        part[(size_t)blockIdx.x * 2 * NRHS + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_cdot_final(const double* __restrict__ part, int nblk, int m2, double* __restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= m2) return;
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t += part[(size_t)b * m2 + k];
+    out[k] = t;
+}
+
+size_t cdot_scratch_doubles(int Vh, int nrhs) { return (size_t)((2 * Vh + 255) / 256) * 2 * nrhs; }
+
+hipError_t launch_cdot(const d2* ae, const d2* be, const d2* ao, const d2* bo, int Vh, int nrhs,
+                       double* scratch, double* out, hipStream_t s)
+{
+    const int nblk = (2 * Vh + 255) / 256;
+    switch (nrhs) {
+#define HISQ_CDOT_CASE(N)                                                                      \
+    case N:                                                                                    \
+        hipLaunchKernelGGL(k_cdot_partial<N>, dim3(nblk), dim3(256), 0, s, ae, be, ao, bo, Vh, \
+                           scratch);                                                           \
+        break;
+        HISQ_CDOT_CASE(1)
+        HISQ_CDOT_CASE(2)
+        HISQ_CDOT_CASE(3)
+        HISQ_CDOT_CASE(4)
+        HISQ_CDOT_CASE(5)
+        HISQ_CDOT_CASE(6)
+        HISQ_CDOT_CASE(7)
+        HISQ_CDOT_CASE(8)
+#undef HISQ_CDOT_CASE
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_cdot_final, dim3(1), dim3(64), 0, s, scratch, nblk, 2 * nrhs, out);
+    return hipGetLastError();
+}
+
 }  // namespace hisq

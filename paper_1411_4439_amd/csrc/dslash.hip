@@ -14,7 +14,7 @@
 //   HISQ_KEPI  one of EPI_PLAIN, EPI_NORM, EPI_CG, EPI_RESID
 #include <type_traits>
 
-#include "hisq_device.h"
+#include "stencil.h"
 
 #ifndef HISQ_KPREC
 #error "HISQ_KPREC must be defined"
@@ -35,58 +35,6 @@ constexpr bool kR14 = false;
 using KT = float;
 constexpr bool kR14 = true;
 #endif
-
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b)
-{
-    return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-
-template <typename C>
-__device__ __forceinline__ C cconj(C a)
-{
-    return C{a.x, -a.y};
-}
-
-// Fused multiply-add in the storage precision (the plain __builtin_fma is the
-// double-precision builtin and would promote FP32 operands).
-__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// acc += m * v in four fused multiply-adds
-template <typename C>
-__device__ __forceinline__ void cfma(C& acc, C m, C v)
-{
-    acc.x = fmadd(m.x, v.x, acc.x);
-    acc.x = fmadd(-m.y, v.y, acc.x);
-    acc.y = fmadd(m.x, v.y, acc.y);
-    acc.y = fmadd(m.y, v.x, acc.y);
-}
-
-__device__ __forceinline__ int wrap_delta(int c, int h, int L)
-{
-    const int cp = c + h;
-    return h + (cp < 0 ? L : 0) - (cp >= L ? L : 0);
-}
-
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F&& f)
-{
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
-template <typename T, bool R14, int S>
-__device__ __forceinline__ void load_link(const cplx<T>* __restrict__ lk, int Vh, int i,
-                                          cplx<T> (&m)[9])
-{
-    const cplx<T>* lp = lk + link_slot_elem(S, R14) * Vh + i;
-    constexpr int ne = (R14 && S >= 8) ? 7 : 9;
-#pragma unroll
-    for (int e = 0; e < ne; ++e) m[e] = __builtin_nontemporal_load(lp + e * Vh);
-}
 
 template <typename T, int NRHS, int NR, bool CM>
 __device__ __forceinline__ void load_vec(const cplx<T>* __restrict__ in, int Vh, int nbr, int g,
@@ -115,43 +63,6 @@ __device__ __forceinline__ void apply_slot(cplx<T> (&m)[9], const cplx<T> (&v)[3
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int k = 0; k < NR; ++k) cfma(acc[a][k], m[3 * a + b], v[b][k]);
-}
-
-// Site coordinates and the neighbour index of slot S = 4*hop + mu, hop
-// (+1, -1, +3, -3), in the other parity's index space.
-struct SiteCoord {
-    int i, row, x, c[4];
-};
-
-__device__ __forceinline__ SiteCoord site_coord(const Lat& lat, int P, int i)
-{
-    SiteCoord sc;
-    int r = i / lat.Lh0;
-    const int xh = i - r * lat.Lh0;
-    sc.c[1] = r % lat.L[1];
-    r /= lat.L[1];
-    sc.c[2] = r % lat.L[2];
-    sc.c[3] = r / lat.L[2];
-    sc.x = 2 * xh + ((P + sc.c[1] + sc.c[2] + sc.c[3]) & 1);
-    sc.c[0] = sc.x;
-    sc.row = i - xh;
-    sc.i = i;
-    return sc;
-}
-
-template <int S>
-__device__ __forceinline__ int neighbour(const Lat& lat, const SiteCoord& sc)
-{
-    constexpr int mu = S & 3;
-    constexpr int hh = S >> 2;
-    constexpr int h = hh == 0 ? 1 : hh == 1 ? -1 : hh == 2 ? 3 : -3;
-    if constexpr (mu == 0) {
-        const int xp = sc.x + wrap_delta(sc.x, h, lat.L[0]);
-        return sc.row + (xp >> 1);
-    } else {
-        const int stride = mu == 1 ? lat.sy : mu == 2 ? lat.sz : lat.st;
-        return sc.i + wrap_delta(sc.c[mu], h, lat.L[mu]) * stride;
-    }
 }
 
 // Pipeline step k -> slot: even steps take the z and t slots, odd steps the x
@@ -463,8 +374,10 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
                     }
                     part[k] += norm2c<T>(rv[k]);
                 }
-                store_rhs<NR, true>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
-                store_rhs<NR, true>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
+                // plain stores: L2 merges the partial lines of consecutive
+                // store instructions before they reach HBM
+                store_rhs<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
+                store_rhs<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
             }
             }
         } else if constexpr (EPI == EPI_RESID) {

@@ -231,6 +231,15 @@ hipError_t launch_accum_sel(d2* xh, f2* xl, size_t ncplx, int nrhs, const CgStat
                             hipStream_t s);
 hipError_t launch_copy_f64(const d2* src, d2* dst, size_t ncplx, hipStream_t s);
 hipError_t launch_layout(const d2* src, d2* dst, int Vh, int nrhs, bool to_colour_major, hipStream_t s);
+hipError_t launch_axpby(const d2* a, const d2* b, d2* out, size_t n, double alpha, double beta,
+                        hipStream_t s);
+size_t cdot_scratch_doubles(int Vh, int nrhs);
+// out[2k], out[2k+1] = re, im of sum conj(a) b over both half fields, rhs k
+hipError_t launch_cdot(const d2* ae, const d2* be, const d2* ao, const d2* bo, int Vh, int nrhs,
+                       double* scratch, double* out, hipStream_t s);
+// d^n D / d mu^n at mu = 0 (n >= 1), FP64 links of the output parity, site-major
+hipError_t launch_dslash_dmu(const Lat& lat, int parity, int nrhs, int nder, const d2* lk,
+                             const d2* in, d2* out, hipStream_t s);
 hipError_t launch_zero_sel(d2* v, size_t ncplx, int nrhs, const CgState* st, hipStream_t s);
 hipError_t launch_redot(const d2* y, const d2* x, int Vh, int nrhs, double scale, double* out,
                         double* red, uint32_t* cnt, hipStream_t s);

@@ -96,6 +96,17 @@ _sig = {
                                              ctypes.POINTER(Info), _P]),
     "hisq_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int]),
+    "hisq_full_workspace_bytes": (ctypes.c_size_t, [_G, ctypes.c_int, ctypes.c_int]),
+    "hisq_trace_workspace_bytes": (ctypes.c_size_t, [_G, ctypes.c_int, ctypes.c_int]),
+    "hisq_dslash_dmu": (ctypes.c_int, [_G, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
+                                       _P]),
+    "hisq_solve_full": (ctypes.c_int, [_G, ctypes.c_double, ctypes.c_int, ctypes.POINTER(Params),
+                                       _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                                       ctypes.POINTER(Info), _P]),
+    "hisq_trace_estimate": (ctypes.c_int, [_G, ctypes.c_double, ctypes.c_int,
+                                           ctypes.POINTER(Params), _P, _P, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_int), _P, _P, _P, _P,
+                                           ctypes.c_size_t, ctypes.POINTER(Info), _P]),
     "hisq_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -281,3 +292,82 @@ def solve(links, mass, b, mode=MODE_FP64, naik=NAIK_FULL, x0=None, ws=None, stre
     status, info = hisq_cg_solve(links.L, mass, n, p, links.f64, l32, b.contiguous(), x, ws,
                                  stream=stream)
     return x, status, info.to_dict(n)
+
+
+def hisq_full_workspace_bytes(L, nrhs, mode):
+    return int(_lib.hisq_full_workspace_bytes(ctypes.byref(geom(L)), nrhs, mode))
+
+
+def hisq_trace_workspace_bytes(L, nrhs, mode):
+    return int(_lib.hisq_trace_workspace_bytes(ctypes.byref(geom(L)), nrhs, mode))
+
+
+def hisq_dslash_dmu(L, out_parity, nrhs, nder, links64, vin, vout, stream=None):
+    _dev_tensor(vin, "in")
+    _dev_tensor(vout, "out")
+    return _check(_lib.hisq_dslash_dmu(ctypes.byref(geom(L)), out_parity, nrhs, nder,
+                                       _ptr(links64), _ptr(vin), _ptr(vout), _stream(stream)),
+                  "hisq_dslash_dmu")
+
+
+def hisq_solve_full(L, mass, nrhs, params, links64, links32, b_e, b_o, x_e, x_o, ws, info=None,
+                    stream=None):
+    for t, nm in ((b_e, "b_e"), (b_o, "b_o"), (x_e, "x_e"), (x_o, "x_o")):
+        _dev_tensor(t, nm)
+    info = info if info is not None else Info()
+    rc = _lib.hisq_solve_full(ctypes.byref(geom(L)), float(mass), nrhs, ctypes.byref(params),
+                              _ptr(links64), _ptr(links32), _ptr(b_e), _ptr(b_o), _ptr(x_e),
+                              _ptr(x_o), _ptr(ws), ws.numel() * ws.element_size(),
+                              ctypes.byref(info), _stream(stream))
+    return _check(rc, "hisq_solve_full"), info
+
+
+def hisq_trace_estimate(L, mass, nrhs, params, links64, links32, orders, eta_e, eta_o, est, ws,
+                        info=None, stream=None):
+    for t, nm in ((eta_e, "eta_e"), (eta_o, "eta_o"), (est, "est")):
+        _dev_tensor(t, nm)
+    info = info if info is not None else Info()
+    arr = (ctypes.c_int * max(1, len(orders)))(*orders)
+    rc = _lib.hisq_trace_estimate(ctypes.byref(geom(L)), float(mass), nrhs, ctypes.byref(params),
+                                  _ptr(links64), _ptr(links32), len(orders), arr, _ptr(eta_e),
+                                  _ptr(eta_o), _ptr(est), _ptr(ws), ws.numel() * ws.element_size(),
+                                  ctypes.byref(info), _stream(stream))
+    return _check(rc, "hisq_trace_estimate"), info
+
+
+def dslash_dmu(links, out_parity, v, nder, stream=None):
+    """d^n D / d mu^n (mu = 0) for a half field v [Vh][3][n] complex128."""
+    out = v.new_empty(v.shape)
+    hisq_dslash_dmu(links.L, out_parity, v.shape[2], nder, links.f64, v.contiguous(), out, stream)
+    return out
+
+
+def solve_full(links, mass, b_e, b_o, mode=MODE_FP64, naik=NAIK_FULL, ws=None, stream=None, **kw):
+    """(x_e, x_o) = M^-1 (b_e, b_o) on the full lattice; returns (x_e, x_o, status, info dict)."""
+    n = b_e.shape[2]
+    p = hisq_default_params(mode=mode, naik=naik, **kw)
+    if ws is None:
+        ws = empty_bytes(hisq_full_workspace_bytes(links.L, n, mode), b_e.device)
+    x_e, x_o = b_e.new_empty(b_e.shape), b_o.new_empty(b_o.shape)
+    l32 = links.packed(PREC_F32, naik) if mode == MODE_MIXED else None
+    status, info = hisq_solve_full(links.L, mass, n, p, links.f64, l32, b_e.contiguous(),
+                                   b_o.contiguous(), x_e, x_o, ws, stream=stream)
+    return x_e, x_o, status, info.to_dict(n)
+
+
+def trace_estimate(links, mass, orders, eta_e, eta_o, mode=MODE_FP64, naik=NAIK_FULL, ws=None,
+                   stream=None, **kw):
+    """Per-vector terms eta_k^dag M^(n_1) M^-1 ... M^(n_j) M^-1 eta_k of eq. (2) for one
+    bundle of noise vectors; returns (complex128 numpy array [n], status, info dict)."""
+    import torch
+    n = eta_e.shape[2]
+    p = hisq_default_params(mode=mode, naik=naik, **kw)
+    if ws is None:
+        ws = empty_bytes(hisq_trace_workspace_bytes(links.L, n, mode), eta_e.device)
+    est = torch.empty((n, 2), dtype=torch.float64, device=eta_e.device)
+    l32 = links.packed(PREC_F32, naik) if mode == MODE_MIXED else None
+    status, info = hisq_trace_estimate(links.L, mass, n, p, links.f64, l32, list(orders),
+                                       eta_e.contiguous(), eta_o.contiguous(), est, ws,
+                                       stream=stream)
+    e = est.cpu().numpy()
+    return e[:, 0] + 1j * e[:, 1], status, info.to_dict(n)

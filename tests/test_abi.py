@@ -27,7 +27,8 @@ def _declared_functions():
 
 def test_header_declares_the_boundary():
     names = _declared_functions()
-    for required in ("hisq_dslash", "hisq_cg_solve", "hisq_cg_solve_backward",
+    for required in ("hisq_dslash", "hisq_cg_solve", "hisq_cg_solve_backward", "hisq_solve_full",
+                     "hisq_dslash_dmu", "hisq_trace_estimate",
                      "hisq_cg_solve_batched", "hisq_pack_links", "hisq_links_bytes",
                      "hisq_workspace_bytes", "hisq_last_error"):
         assert required in names
@@ -77,6 +78,9 @@ def test_workspace_bytes(H):
     assert H.hisq_workspace_bytes(L, 0, H.MODE_FP64) == 0
     assert H.hisq_workspace_bytes(L, 9, H.MODE_FP64) == 0
     assert H.hisq_workspace_bytes(L, 1, 7) == 0
+    wf = H.hisq_full_workspace_bytes(L, 4, H.MODE_MIXED)
+    assert wf >= wmx + 2 * Vh * 3 * 4 * 16
+    assert H.hisq_trace_workspace_bytes(L, 4, H.MODE_MIXED) >= wf + 4 * Vh * 3 * 4 * 16
 
 
 def test_errors_before_any_launch(H):
@@ -113,6 +117,22 @@ def test_errors_before_any_launch(H):
     assert rc == H.HISQ_EINVAL
     rc = lib.hisq_cg_solve_batched(0, None, ctypes.byref(p), fake, 0, None, None)
     assert rc == H.HISQ_EINVAL
+    # full solve and trace estimator: mass 0 cannot give x_o; bad insertion lists
+    rc = lib.hisq_solve_full(ctypes.byref(g), 0.0, 1, ctypes.byref(p), fake, None, fake, fake, fake,
+                             fake, fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL and "mass" in H.hisq_last_error()
+    orders = (ctypes.c_int * 2)(1, 9)
+    rc = lib.hisq_trace_estimate(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, 2, orders,
+                                 fake, fake, fake, fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL and "orders[1]" in H.hisq_last_error()
+    rc = lib.hisq_trace_estimate(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, 0, orders,
+                                 fake, fake, fake, fake, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL
+    rc = lib.hisq_dslash_dmu(ctypes.byref(g), 0, 1, -1, fake, fake, fake, None)
+    assert rc == H.HISQ_EINVAL
+    rc = lib.hisq_solve_full(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, fake, fake, fake,
+                             fake, fake, 16, ctypes.byref(info), None)
+    assert rc == H.HISQ_EWORKSPACE
 
 
 def test_tuning_control(H):
