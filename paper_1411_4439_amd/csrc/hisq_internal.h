@@ -96,6 +96,20 @@ __host__ __device__ constexpr int link_slot_elem(int slot, bool r14)
     return slot < 8 ? 9 * slot : 72 + (r14 ? 7 : 9) * (slot - 8);
 }
 
+// Position of element e (0 <= e < ne, ne = 9, or 7 for an r14 Naik slot) of
+// site i's matrix, in complex numbers from the slot's start.  FP64: [e][Vh].
+// FP32: elements pair up into 16-byte words, [e/2][Vh][2], so that one load
+// brings two of them; the odd last element has a plane [Vh] of its own after
+// the words.  Same bytes either way.
+template <typename T>
+__host__ __device__ inline size_t link_elem_offset(int e, int ne, int Vh, int i)
+{
+    if (sizeof(T) == 8) return (size_t)e * Vh + i;
+    const int nw = ne / 2;
+    if (e < 2 * nw) return ((size_t)(e >> 1) * Vh + i) * 2 + (e & 1);
+    return (size_t)2 * nw * Vh + i;
+}
+
 // Per-problem CG scalars, in device memory (FP64).
 struct CgState {
     double rr[kMaxRhs];      // current (iterated) |r|^2

@@ -63,7 +63,7 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
                 for (int b = 0; b < 3; ++b) t[3 * a + b] = d2{-m[3 * b + a].x, m[3 * b + a].y};
             for (int e = 0; e < 9; ++e) m[e] = t[e];
         }
-        C* dst = blk + (size_t)link_slot_elem(slot, R14) * Vh + i;
+        C* dst = blk + (size_t)link_slot_elem(slot, R14) * Vh;
         if (R14 && slot >= 8) {
             // w = conj(row0 x row1); c = <w, row2> / |w|^2
             d2 w[3];
@@ -86,10 +86,10 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
             const double rel = fro > 0 ? sqrt(err / fro) : 0.0;
             const float relf = (rel == rel) ? (float)rel : 3.0e38f;
             worst = fmaxf(worst, relf);
-            for (int e = 0; e < 6; ++e) dst[(size_t)e * Vh] = C{(T)m[e].x, (T)m[e].y};
-            dst[(size_t)6 * Vh] = C{(T)cc.x, (T)cc.y};
+            for (int e = 0; e < 6; ++e) dst[link_elem_offset<T>(e, 7, Vh, i)] = C{(T)m[e].x, (T)m[e].y};
+            dst[link_elem_offset<T>(6, 7, Vh, i)] = C{(T)cc.x, (T)cc.y};
         } else {
-            for (int e = 0; e < 9; ++e) dst[(size_t)e * Vh] = C{(T)m[e].x, (T)m[e].y};
+            for (int e = 0; e < 9; ++e) dst[link_elem_offset<T>(e, 9, Vh, i)] = C{(T)m[e].x, (T)m[e].y};
         }
     }
     if (R14 && worst > 0.0f) atomicMax(&hdr->r14_err_bits, __float_as_uint(worst));

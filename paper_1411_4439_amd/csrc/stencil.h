@@ -51,14 +51,30 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
+// Link matrix of slot S for site i into m[0..ne-1] (ne = 9, or 7 for an r14
+// Naik slot), non-temporal (no reuse within a half-Dslash).  FP32 reads 16-byte
+// words of two elements: the same bytes in fewer, wider requests, which is
+// measurably faster than one 8-byte read per element.
 template <typename T, bool R14, int S>
 __device__ __forceinline__ void load_link(const cplx<T>* __restrict__ lk, int Vh, int i,
                                           cplx<T> (&m)[9])
 {
-    const cplx<T>* lp = lk + link_slot_elem(S, R14) * Vh + i;
+    const cplx<T>* lp = lk + link_slot_elem(S, R14) * Vh;
     constexpr int ne = (R14 && S >= 8) ? 7 : 9;
+    if constexpr (sizeof(T) == 4) {
+        constexpr int nw = ne / 2;
+        const f4* wp = reinterpret_cast<const f4*>(lp) + i;
 #pragma unroll
-    for (int e = 0; e < ne; ++e) m[e] = __builtin_nontemporal_load(lp + e * Vh);
+        for (int w = 0; w < nw; ++w) {
+            const f4 q = __builtin_nontemporal_load(wp + (size_t)w * Vh);
+            m[2 * w] = cplx<T>{q.x, q.y};
+            m[2 * w + 1] = cplx<T>{q.z, q.w};
+        }
+        m[ne - 1] = __builtin_nontemporal_load(lp + (size_t)2 * nw * Vh + i);
+    } else {
+#pragma unroll
+        for (int e = 0; e < ne; ++e) m[e] = __builtin_nontemporal_load(lp + (size_t)e * Vh + i);
+    }
 }
 
 // Site coordinates and the neighbour index of slot S = 4*hop + mu, hop
