@@ -123,7 +123,7 @@ def main():
     b = W.make_sources(L, n, W.sources_seed(3))
     log("generated links and sources in %.1f s" % (time.time() - t0))
     Ud, Nd, bd = dev(U), dev(N), dev(b)
-    links = H.Links(L, Ud, Nd)
+    links = H.Links(L, Ud, Nd, r13=not args.no_sweep)
     torch.cuda.synchronize()
     if args.tile != "auto":
         nr, order, rows = (int(v) for v in args.tile.split(","))
@@ -265,7 +265,8 @@ def main():
         cases = [(prec, nk2, tag, nn, H.LAYOUT_COLOUR)
                  for prec, nk2, tag in ((H.PREC_F64, H.NAIK_FULL, "f64"),
                                         (H.PREC_F32, H.NAIK_FULL, "f32"),
-                                        (H.PREC_F32, H.NAIK_R14, "f32_r14"))
+                                        (H.PREC_F32, H.NAIK_R14, "f32_r14"),
+                                        (H.PREC_F32, H.NAIK_R13, "f32_r13"))
                  for nn in (1, 2, 4, 8)]
         cases.append((H.PREC_F32, H.NAIK_R14, "f32_r14_sitemajor", n, H.LAYOUT_SITE))
         for prec, nk2, tag, nn, lay in cases:
@@ -287,7 +288,8 @@ def main():
                 ev1.synchronize()
                 ms = ev0.elapsed_time(ev1) / reps
                 scale = 2 if prec == H.PREC_F64 else 1
-                byt = Vh * scale * (R.LINK_BYTES_F32["r14" if nk2 == H.NAIK_R14 else "full"] + 2 * vec_b * nn)
+                kname = {H.NAIK_R14: "r14", H.NAIK_R13: "r13"}.get(nk2, "full")
+                byt = Vh * scale * (R.LINK_BYTES_F32[kname] + 2 * vec_b * nn)
                 sweep["%s_n%d" % (tag, nn)] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
                                                "GFlops": round(Vh * R.FLOPS_PER_SITE_RHS * nn / ms / 1e6, 1)}
         result["dslash_sweep"] = sweep

@@ -13,7 +13,7 @@
  *     periodic 4-D lattice; U, N are complex 3x3, fields complex 3-vectors.
  *   - A bundle of n rhs is n independent applications of D sharing each link
  *     load (eq. (4)).
- *   - Naik links may be stored with 14 reals ("r14", Table 1).
+ *   - Naik links may be stored with 14 reals ("r14", Table 1) or 13 ("r13").
  *   - The fermion matrix is read as M = 2m + D; D is anti-Hermitian and only
  *     couples opposite parities, so the even block of M^dag M is
  *     A = 4 m^2 - D_eo D_oe, Hermitian positive definite (lambda_min >= 4 m^2).
@@ -63,7 +63,7 @@ extern "C" {
 #define HISQ_EINVAL (-1)      /* null pointer, n outside 1..8, tol <= 0, bad enum   */
 #define HISQ_EGEOM (-2)       /* an extent odd or < 4                               */
 #define HISQ_EWORKSPACE (-3)  /* workspace smaller than hisq_workspace_bytes()      */
-#define HISQ_EPACK (-4)       /* r14 round-trip error above 1e-6 * |N| (not s*U(3)) */
+#define HISQ_EPACK (-4)       /* r14/r13 round-trip error above 1e-6 |N| (not s*U(3)) */
 #define HISQ_EHIP (-5)        /* a HIP runtime call failed                           */
 #define HISQ_NOT_CONVERGED 1  /* maxiter reached before the true residual passed    */
 #define HISQ_BREAKDOWN 2      /* <p, A p> <= 0 or not finite                         */
@@ -74,7 +74,11 @@ extern "C" {
 #define HISQ_MAX_INSERTIONS 8   /* operator insertions per hisq_trace_estimate term   */
 
 enum hisq_prec { HISQ_PREC_F64 = 0, HISQ_PREC_F32 = 1 };
-enum hisq_naik { HISQ_NAIK_FULL = 0, HISQ_NAIK_R14 = 1 };
+/* Naik link storage (Sec. 1: reconstruction from fewer floats, Table 1 "r14"):
+ * FULL 18 reals; R14 rows 0, 1 and one complex c with row2 = c conj(row0 x row1);
+ * R13 rows 0, 1 and the phase phi of c, |c| = 1 / |row0|.  R14 and R13 are exact
+ * for N = s V with V in U(3), s > 0, and FP32 only. */
+enum hisq_naik { HISQ_NAIK_FULL = 0, HISQ_NAIK_R14 = 1, HISQ_NAIK_R13 = 2 };
 enum hisq_mode { HISQ_MODE_FP64 = 0, HISQ_MODE_MIXED = 1 };
 /* field order: [Vh][3][n] (site-major, the default) or [3][Vh][n] */
 enum hisq_layout { HISQ_LAYOUT_SITE = 0, HISQ_LAYOUT_COLOUR = 1 };
@@ -139,7 +143,7 @@ void hisq_default_params(hisq_params* p);
 
 /*
  * Size in bytes of a packed link buffer for `prec` (HISQ_PREC_*) and Naik
- * storage `naik` (HISQ_NAIK_*; R14 only with F32).  0 on invalid input.
+ * storage `naik` (HISQ_NAIK_*; R14 and R13 only with F32).  0 on invalid input.
  */
 size_t hisq_links_bytes(const hisq_geom* g, int prec, int naik);
 
@@ -164,9 +168,11 @@ size_t hisq_trace_workspace_bytes(const hisq_geom* g, int nrhs, int mode);
  * Pack canonical links U, N ([4][V][3][3] complex128, device) into `packed`
  * (device, hisq_links_bytes(g, prec, naik) bytes) for the Dslash of eq. (3).
  * For naik = R14 every Naik link (and its adjoint) is stored as rows 0, 1 and
- * one complex c with row2 = c conj(row0 x row1); the call then synchronizes
- * `stream` and returns HISQ_EPACK if any round-trip error exceeds 1e-6 of the
- * link's norm (N is not a positive multiple of a U(3) matrix).
+ * one complex c with row2 = c conj(row0 x row1); for R13 as rows 0, 1 and the
+ * phase of c, whose modulus 1/|row0| follows from N = s V, V in U(3).  Both
+ * then synchronize `stream` and return HISQ_EPACK if any round-trip error
+ * exceeds 1e-6 of the link's norm (N is not a positive multiple of a U(3)
+ * matrix).
  */
 int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int prec, int naik,
                     void* packed, void* stream);

@@ -63,6 +63,8 @@ def _load():
             lib.orc_r14_pack.argtypes = [ctypes.c_long, P, P, P]
             lib.orc_r14_unpack.argtypes = [ctypes.c_long, P, P]
             lib.orc_dslash_chem_eo.argtypes = [Lp, I, I, P, P, D, I, P, P]
+            lib.orc_r13_pack.argtypes = [ctypes.c_long, P, P, P]
+            lib.orc_r13_unpack.argtypes = [ctypes.c_long, P, P]
             lib.orc_num_threads.argtypes = []
             _lib = lib
     return _lib
@@ -197,6 +199,27 @@ def r14_unpack(P):
     count = int(np.prod(lead)) if lead else 1
     M = np.empty(lead + (3, 3), dtype=np.complex128)
     _check(_load().orc_r14_unpack(count, _ptr(P), _ptr(M)))
+    return M
+
+
+def r13_pack(M):
+    """Compress (..., 3, 3) complex matrices to (..., 13) reals; returns (packed, max_err)."""
+    M = _c128(M)
+    lead = M.shape[:-2]
+    count = int(np.prod(lead)) if lead else 1
+    out = np.empty(lead + (13,), dtype=np.float64)
+    err = np.zeros(1)
+    _check(_load().orc_r13_pack(count, _ptr(M), _ptr(out), _ptr(err)))
+    return out, float(err[0])
+
+
+def r13_unpack(P):
+    """Inverse of r13_pack."""
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    lead = P.shape[:-1]
+    count = int(np.prod(lead)) if lead else 1
+    M = np.empty(lead + (3, 3), dtype=np.complex128)
+    _check(_load().orc_r13_unpack(count, _ptr(P), _ptr(M)))
     return M
 
 

@@ -27,6 +27,9 @@
  *   orc_r14_pack /    the 14-real compressed Naik storage of Sec. 1 (Table 1,
  *   orc_r14_unpack    "r14"): rows 0 and 1 plus one complex c with
  *                     row2 = c * conj(row0 x row1), exact for N = s * U(3).
+ *   orc_r13_pack /    13 reals: rows 0 and 1 plus the phase phi of that c; its
+ *   orc_r13_unpack    modulus follows from N = s V, V in U(3): |row0| = s, and
+ *                     row2 = s det(V) conj(v0 x v1) = (e^{i phi} / s) conj(row0 x row1).
  *   orc_dslash_chem_eo
  *                     d^n/dmu^n of the Dslash at quark chemical potential mu,
  *                     one output parity: the operators dM/dmu of Sec. 1 eq. (2).
@@ -615,6 +618,59 @@ int orc_r14_unpack(long count, const double* packed, double* M)
         zc cr[3];
         cross_conj(W, W + 3, cr);
         for (int j = 0; j < 3; ++j) W[6 + j] = c * cr[j];
+    }
+    return 0;
+}
+
+/*
+ * r13: rows 0 and 1 (12 reals) and phi = arg(c), where for N = s V, V in U(3),
+ * row2 = c conj(row0 x row1) with c = det(V) / s and s = |row0|.  Here phi is
+ * taken from det(N) = s^3 det(V); max_err as for r14.
+ */
+int orc_r13_unpack(long count, const double* packed, double* M);
+
+int orc_r13_pack(long count, const double* M, double* packed, double* max_err)
+{
+    if (count < 0 || !M || !packed || !max_err) return -1;
+    const zc* A = (const zc*)M;
+    double worst = 0;
+    for (long j = 0; j < count; ++j) {
+        const zc* m = A + 9 * j;
+        double* p = packed + 13 * j;
+        for (int e = 0; e < 6; ++e) {
+            p[2 * e] = creal(m[e]);
+            p[2 * e + 1] = cimag(m[e]);
+        }
+        const zc det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                       m[2] * (m[3] * m[7] - m[4] * m[6]);
+        p[12] = carg(det);
+        zc back[9];
+        orc_r13_unpack(1, p, (double*)back);
+        double err = 0, fro = 0;
+        for (int e = 0; e < 9; ++e) {
+            err += cabs(back[e] - m[e]) * cabs(back[e] - m[e]);
+            fro += cabs(m[e]) * cabs(m[e]);
+        }
+        const double rel = fro > 0 ? sqrt(err / fro) : 0;
+        if (!(rel <= worst)) worst = rel;
+    }
+    *max_err = worst;
+    return 0;
+}
+
+int orc_r13_unpack(long count, const double* packed, double* M)
+{
+    if (count < 0 || !packed || !M) return -1;
+    zc* A = (zc*)M;
+    for (long j = 0; j < count; ++j) {
+        const double* p = packed + 13 * j;
+        zc* m = A + 9 * j;
+        for (int e = 0; e < 6; ++e) m[e] = p[2 * e] + I * p[2 * e + 1];
+        const double s = sqrt(creal(m[0] * conj(m[0]) + m[1] * conj(m[1]) + m[2] * conj(m[2])));
+        const zc c = s > 0 ? cexp(I * p[12]) / s : 0;
+        zc w[3];
+        cross_conj(m, m + 3, w);
+        for (int k = 0; k < 3; ++k) m[6 + k] = c * w[k];
     }
     return 0;
 }

@@ -23,7 +23,8 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wno-unused-command-line-argument"]
 
-DSLASH_VARIANTS = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (2, 2)]
+DSLASH_VARIANTS = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (2, 2),
+                   (3, 0), (3, 1), (3, 2)]
 OTHER_SOURCES = ["blas.hip", "pack.hip", "force.hip", "dmu.hip", "dispatch.cpp", "api.cpp"]
 
 

@@ -150,25 +150,26 @@ size_t ws_layout(const Lat& lat, int n, int mode, int kind, char* base, Ws* w)
 // ---------------------------------------------------------------------------
 // Packed link access.
 template <typename T>
-const cplx<T>* link_block(const void* packed, int Vh, bool r14, int parity)
+const cplx<T>* link_block(const void* packed, int Vh, int nk, int parity)
 {
     const char* b = reinterpret_cast<const char*>(packed) + kLinkHeaderBytes;
-    return reinterpret_cast<const cplx<T>*>(b) + (size_t)parity * link_block_elems(Vh, r14);
+    return reinterpret_cast<const cplx<T>*>(reinterpret_cast<const T*>(b) +
+                                            (size_t)parity * link_block_reals(Vh, nk));
 }
 
 // cm: colour-major fields (every solver launch); false only for the plain
 // Dslash on canonical site-major fields.
-hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<double>& a,
+hipError_t launch_ds(int epi, int n, int nk, const Tile& t, const DslashArgs<double>& a,
                      hipStream_t s, bool cm = true)
 {
-    (void)r14;
+    (void)nk;
     return launch_dslash_f64(epi, n, t, a, s, cm);
 }
 
-hipError_t launch_ds(int epi, int n, bool r14, const Tile& t, const DslashArgs<float>& a,
+hipError_t launch_ds(int epi, int n, int nk, const Tile& t, const DslashArgs<float>& a,
                      hipStream_t s, bool cm = true)
 {
-    return r14 ? launch_dslash_f32r14(epi, n, t, a, s, cm) : launch_dslash_f32(epi, n, t, a, s, cm);
+    return launch_dslash_f32(epi, nk, n, t, a, s, cm);
 }
 
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStream_t s)
@@ -246,7 +247,7 @@ std::string tune_key(const Lat& lat, int n, int prec, int naik, int epi, bool cm
 // solver's reducing kernel, whose per-work-group reduction cost depends on the
 // tile (probe.state/red/cnt must then be valid, counters zero, rhs active).
 template <typename T>
-int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& probe, hipStream_t s,
+int get_tile(const Lat& lat, int n, int prec, int nk, const DslashArgs<T>& probe, hipStream_t s,
              Tile* out, int epi = EPI_PLAIN, bool cm = true)
 {
     int mode, fnr, fbs, ford, frows;
@@ -269,7 +270,7 @@ int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& pro
         *out = default_tile(n, prec);
         return HISQ_OK;
     }
-    const std::string key = tune_key(lat, n, prec, r14 ? 1 : 0, epi, cm);
+    const std::string key = tune_key(lat, n, prec, nk, epi, cm);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -301,9 +302,9 @@ int get_tile(const Lat& lat, int n, int prec, bool r14, const DslashArgs<T>& pro
                 Tile c = base;
                 c.remap = remap;
                 if (!t_order_ok(lat, G, c.bs, remap)) continue;
-                if (launch_ds(epi, n, r14, c, probe, s, cm) != hipSuccess) continue;
+                if (launch_ds(epi, n, nk, c, probe, s, cm) != hipSuccess) continue;
                 HIP_TRY(hipEventRecord(e0, s));
-                for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, r14, c, probe, s, cm));
+                for (int rep = 0; rep < 3; ++rep) HIP_TRY(launch_ds(epi, n, nk, c, probe, s, cm));
                 HIP_TRY(hipEventRecord(e1, s));
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0;
@@ -389,7 +390,8 @@ struct Prob {
 struct Engine {
     std::vector<Prob> P;
     hisq_params prm{};
-    bool mixed = false, r14 = false;
+    bool mixed = false;
+    int nk = HISQ_NAIK_FULL;  // Naik storage of the FP32 links (MIXED)
     hipStream_t s = nullptr;
     CgState* states = nullptr;  // device, contiguous, one per problem
     void* table = nullptr;      // device BatchTable (several problems)
@@ -404,7 +406,7 @@ struct Engine {
         DslashArgs<double> a{};
         a.lat = q.lat;
         a.parity = parity;
-        a.links = link_block<double>(q.links64, q.lat.Vh, false, parity);
+        a.links = link_block<double>(q.links64, q.lat.Vh, HISQ_NAIK_FULL, parity);
         a.mass4 = q.m4;
         a.state = q.w.st;
         a.red = q.w.red;
@@ -418,13 +420,13 @@ struct Engine {
         DslashArgs<double> a = args64(q, 1);
         a.in = q.x;
         a.out = q.w.t64;
-        HIP_TRY(launch_ds(EPI_PLAIN, q.n, false, q.t64, a, s));
+        HIP_TRY(launch_ds(EPI_PLAIN, q.n, HISQ_NAIK_FULL, q.t64, a, s));
         DslashArgs<double> c = args64(q, 0);
         c.in = q.w.t64;
         c.out = q.w.r64;
         c.b = q.b;
         c.xh = q.x;
-        HIP_TRY(launch_ds(EPI_RESID, q.n, false, q.t64, c, s));
+        HIP_TRY(launch_ds(EPI_RESID, q.n, HISQ_NAIK_FULL, q.t64, c, s));
         return HISQ_OK;
     }
 
@@ -432,7 +434,7 @@ struct Engine {
     void iter_args(const Prob& q, PupdateArgs<T>& k1, DslashArgs<T>& k2, DslashArgs<T>& k3) const
     {
         const void* L = std::is_same<T, float>::value ? q.links32 : q.links64;
-        const bool rr = r14 && std::is_same<T, float>::value;
+        const int rr = std::is_same<T, float>::value ? nk : HISQ_NAIK_FULL;
         cplx<T>* r;
         cplx<T>* p;
         cplx<T>* t;
@@ -486,7 +488,7 @@ struct Engine {
         DslashArgs<T> k2, k3;
         iter_args<T>(q, k1, k2, k3);
         const Tile& tile = std::is_same<T, float>::value ? q.t32 : q.t64;
-        const bool rr = r14 && std::is_same<T, float>::value;
+        const int rr = std::is_same<T, float>::value ? nk : HISQ_NAIK_FULL;
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
         HIP_TRY(launch_pup(q.n, tile, k1, st));
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
@@ -505,9 +507,9 @@ struct Engine {
         if constexpr (std::is_same<T, float>::value) {
             HIP_TRY(launch_pupdate_batched_f32(tab, batch_blocks, batch_bs, st));
             if (evs) HIP_TRY(hipEventRecord(evs[1], st));
-            HIP_TRY(launch_dslash_batched_f32(EPI_NORM, r14, tab, batch_blocks, batch_bs, st));
+            HIP_TRY(launch_dslash_batched_f32(EPI_NORM, nk, tab, batch_blocks, batch_bs, st));
             if (evs) HIP_TRY(hipEventRecord(evs[2], st));
-            HIP_TRY(launch_dslash_batched_f32(EPI_CG, r14, tab, batch_blocks, batch_bs, st));
+            HIP_TRY(launch_dslash_batched_f32(EPI_CG, nk, tab, batch_blocks, batch_bs, st));
         } else {
             HIP_TRY(launch_pupdate_batched_f64(tab, batch_blocks, batch_bs, st));
             if (evs) HIP_TRY(hipEventRecord(evs[1], st));
@@ -835,19 +837,19 @@ int Engine::run(hisq_info* infos)
         DslashArgs<double> probe = args64(q, 1);
         probe.in = q.x;
         probe.out = q.w.t64;
-        if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F64, false, probe, s, &q.t64, EPI_NORM))) return rc;
+        if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F64, HISQ_NAIK_FULL, probe, s, &q.t64, EPI_NORM))) return rc;
         if (mixed) {
             DslashArgs<float> p32{};
             p32.lat = q.lat;
             p32.parity = 1;
-            p32.links = link_block<float>(q.links32, q.lat.Vh, r14, 1);
+            p32.links = link_block<float>(q.links32, q.lat.Vh, nk, 1);
             p32.in = q.w.p32;
             p32.out = q.w.t32;
             p32.mass4 = q.m4;
             p32.state = q.w.st;
             p32.red = q.w.red;
             p32.cnt = q.w.cnt;
-            if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F32, r14, p32, s, &q.t32, EPI_NORM))) return rc;
+            if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F32, nk, p32, s, &q.t32, EPI_NORM))) return rc;
         }
     }
     if ((rc = setup(host))) return rc;
@@ -915,7 +917,7 @@ int check_params(const hisq_params* p, int n)
     if (n < 1 || n > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", n);
     if (p->mode != HISQ_MODE_FP64 && p->mode != HISQ_MODE_MIXED)
         return fail(HISQ_EINVAL, "unknown mode %d", p->mode);
-    if (p->naik != HISQ_NAIK_FULL && p->naik != HISQ_NAIK_R14)
+    if (p->naik != HISQ_NAIK_FULL && p->naik != HISQ_NAIK_R14 && p->naik != HISQ_NAIK_R13)
         return fail(HISQ_EINVAL, "unknown naik storage %d", p->naik);
     if (!(p->tol > 0) || !std::isfinite(p->tol)) return fail(HISQ_EINVAL, "tol must be > 0");
     if (p->maxiter < 0) return fail(HISQ_EINVAL, "maxiter must be >= 0");
@@ -932,7 +934,7 @@ int solve_impl(double mass, int nrhs, const hisq_params* p, const void* links64,
     Engine E;
     E.prm = *p;
     E.mixed = p->mode == HISQ_MODE_MIXED;
-    E.r14 = E.mixed && p->naik == HISQ_NAIK_R14;
+    E.nk = E.mixed ? p->naik : HISQ_NAIK_FULL;
     E.s = reinterpret_cast<hipStream_t>(stream);
     Prob q;
     q.lat = lat;
@@ -963,10 +965,10 @@ int full_impl(double mass, int n, const hisq_params* p, const void* links64, con
     DslashArgs<double> a{};
     a.lat = lat;
     a.parity = 0;
-    a.links = link_block<double>(links64, lat.Vh, false, 0);
+    a.links = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, 0);
     a.in = b_o;
     a.out = w.fo;
-    HIP_TRY(launch_ds(EPI_PLAIN, n, false, t, a, s, false));
+    HIP_TRY(launch_ds(EPI_PLAIN, n, HISQ_NAIK_FULL, t, a, s, false));
     HIP_TRY(launch_axpby(b_e, w.fo, w.bp, nc, 2.0 * mass, -1.0, s));
     hisq_params q = *p;
     q.use_x0 = 0;
@@ -974,10 +976,10 @@ int full_impl(double mass, int n, const hisq_params* p, const void* links64, con
                               reinterpret_cast<double*>(x_e), w, info, s, lat);
     if (st < 0) return st;
     a.parity = 1;
-    a.links = link_block<double>(links64, lat.Vh, false, 1);
+    a.links = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, 1);
     a.in = x_e;
     a.out = w.fo;
-    HIP_TRY(launch_ds(EPI_PLAIN, n, false, t, a, s, false));
+    HIP_TRY(launch_ds(EPI_PLAIN, n, HISQ_NAIK_FULL, t, a, s, false));
     HIP_TRY(launch_axpby(b_o, w.fo, x_o, nc, 1.0 / (2.0 * mass), -1.0 / (2.0 * mass), s));
     return st;
 }
@@ -988,9 +990,9 @@ int apply_dM(double mass, int n, int nder, const void* links64, const d2* x_e, c
 {
     const size_t nc = (size_t)lat.Vh * 3 * n;
     if (nder > 0) {
-        HIP_TRY(launch_dslash_dmu(lat, 0, n, nder, link_block<double>(links64, lat.Vh, false, 0), x_o,
+        HIP_TRY(launch_dslash_dmu(lat, 0, n, nder, link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, 0), x_o,
                                   y_e, s));
-        HIP_TRY(launch_dslash_dmu(lat, 1, n, nder, link_block<double>(links64, lat.Vh, false, 1), x_e,
+        HIP_TRY(launch_dslash_dmu(lat, 1, n, nder, link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, 1), x_e,
                                   y_o, s));
         return HISQ_OK;
     }
@@ -999,10 +1001,10 @@ int apply_dM(double mass, int n, int nder, const void* links64, const d2* x_e, c
     a.lat = lat;
     for (int par = 0; par < 2; ++par) {
         a.parity = par;
-        a.links = link_block<double>(links64, lat.Vh, false, par);
+        a.links = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, par);
         a.in = par == 0 ? x_o : x_e;
         a.out = w.fo;
-        HIP_TRY(launch_ds(EPI_PLAIN, n, false, t, a, s, false));
+        HIP_TRY(launch_ds(EPI_PLAIN, n, HISQ_NAIK_FULL, t, a, s, false));
         HIP_TRY(launch_axpby(par == 0 ? x_e : x_o, w.fo, par == 0 ? y_e : y_o, nc, 2.0 * mass, 1.0, s));
     }
     return HISQ_OK;
@@ -1114,10 +1116,10 @@ size_t hisq_links_bytes(const hisq_geom* g, int prec, int naik)
     Lat lat;
     if (check_geom(g, &lat)) return 0;
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return 0;
-    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return 0;
-    if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32) return 0;
+    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13) return 0;
+    if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32) return 0;
     const size_t elem = prec == HISQ_PREC_F64 ? sizeof(d2) : sizeof(f2);
-    return kLinkHeaderBytes + 2 * link_block_elems(lat.Vh, naik == HISQ_NAIK_R14) * elem;
+    return kLinkHeaderBytes + 2 * link_block_reals(lat.Vh, naik) * (elem / 2);
 }
 
 size_t hisq_workspace_bytes(const hisq_geom* g, int nrhs, int mode)
@@ -1169,21 +1171,23 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
     if (rc) return rc;
     if (!U || !N || !packed) return fail(HISQ_EINVAL, "NULL pointer");
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
-    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return fail(HISQ_EINVAL, "bad naik %d", naik);
-    if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32)
-        return fail(HISQ_EINVAL, "r14 Naik storage is FP32 only");
+    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13)
+        return fail(HISQ_EINVAL, "bad naik %d", naik);
+    if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32)
+        return fail(HISQ_EINVAL, "r14 / r13 Naik storage is FP32 only");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(launch_pack(lat, reinterpret_cast<const d2*>(U), reinterpret_cast<const d2*>(N), prec,
                         naik, packed, s));
-    if (naik == HISQ_NAIK_R14) {
+    if (naik != HISQ_NAIK_FULL) {
         uint32_t bits = 0;
         const LinkHeader* h = reinterpret_cast<const LinkHeader*>(packed);
-        HIP_TRY(hipMemcpyAsync(&bits, &h->r14_err_bits, sizeof(bits), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&bits, &h->naik_err_bits, sizeof(bits), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         float err;
         std::memcpy(&err, &bits, sizeof(err));
-        if (!(err <= kR14Tolerance))
-            return fail(HISQ_EPACK, "r14 round-trip error %g: Naik links are not s * U(3)", err);
+        if (!(err <= kNaikTolerance))
+            return fail(HISQ_EPACK, "%s round-trip error %g: Naik links are not s * U(3)",
+                        naik == HISQ_NAIK_R14 ? "r14" : "r13", err);
     }
     return HISQ_OK;
 }
@@ -1199,33 +1203,34 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
     if (out_parity != 0 && out_parity != 1) return fail(HISQ_EINVAL, "out_parity must be 0 or 1");
     if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", nrhs);
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
-    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14) return fail(HISQ_EINVAL, "bad naik %d", naik);
-    if (naik == HISQ_NAIK_R14 && prec != HISQ_PREC_F32)
-        return fail(HISQ_EINVAL, "r14 Naik storage is FP32 only");
+    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13)
+        return fail(HISQ_EINVAL, "bad naik %d", naik);
+    if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32)
+        return fail(HISQ_EINVAL, "r14 / r13 Naik storage is FP32 only");
     if (layout != HISQ_LAYOUT_SITE && layout != HISQ_LAYOUT_COLOUR)
         return fail(HISQ_EINVAL, "bad layout %d", layout);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const bool r14 = naik == HISQ_NAIK_R14;
+    const int nk = naik;
     const bool cm = layout == HISQ_LAYOUT_COLOUR;
     Tile t;
     if (prec == HISQ_PREC_F64) {
         DslashArgs<double> a{};
         a.lat = lat;
         a.parity = out_parity;
-        a.links = link_block<double>(packed, lat.Vh, false, out_parity);
+        a.links = link_block<double>(packed, lat.Vh, HISQ_NAIK_FULL, out_parity);
         a.in = reinterpret_cast<const d2*>(in);
         a.out = reinterpret_cast<d2*>(out);
-        if ((rc = get_tile(lat, nrhs, prec, false, a, s, &t, EPI_PLAIN, cm))) return rc;
-        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s, cm));
+        if ((rc = get_tile(lat, nrhs, prec, HISQ_NAIK_FULL, a, s, &t, EPI_PLAIN, cm))) return rc;
+        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, cm));
     } else {
         DslashArgs<float> a{};
         a.lat = lat;
         a.parity = out_parity;
-        a.links = link_block<float>(packed, lat.Vh, r14, out_parity);
+        a.links = link_block<float>(packed, lat.Vh, nk, out_parity);
         a.in = reinterpret_cast<const f2*>(in);
         a.out = reinterpret_cast<f2*>(out);
-        if ((rc = get_tile(lat, nrhs, prec, r14, a, s, &t, EPI_PLAIN, cm))) return rc;
-        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, r14, t, a, s, cm));
+        if ((rc = get_tile(lat, nrhs, prec, nk, a, s, &t, EPI_PLAIN, cm))) return rc;
+        HIP_TRY(launch_ds(EPI_PLAIN, nrhs, nk, t, a, s, cm));
     }
     return HISQ_OK;
 }
@@ -1284,13 +1289,13 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     DslashArgs<double> a{};
     a.lat = lat;
     a.parity = 1;
-    a.links = link_block<double>(links64, lat.Vh, false, 1);
+    a.links = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, 1);
     a.in = reinterpret_cast<const d2*>(x_e);
     a.out = w.tx;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s, false));  // caller's site-major fields
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, false));  // caller's site-major fields
     a.in = y;
     a.out = w.sy;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, t, a, s, false));
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, false));
     HIP_TRY(launch_force(lat, nrhs, reinterpret_cast<const d2*>(x_e), y, w.tx, w.sy,
                          reinterpret_cast<d2*>(grad_U), reinterpret_cast<d2*>(grad_N), s));
     HIP_TRY(launch_redot(y, reinterpret_cast<const d2*>(x_e), lat.Vh, nrhs, -8.0 * mass, grad_m,
@@ -1314,7 +1319,7 @@ int hisq_dslash_dmu(const hisq_geom* g, int out_parity, int nrhs, int nder, cons
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const d2* vin = reinterpret_cast<const d2*>(in);
     d2* vout = reinterpret_cast<d2*>(out);
-    const d2* lk = link_block<double>(links64, lat.Vh, false, out_parity);
+    const d2* lk = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, out_parity);
     if (nder > 0) {
         HIP_TRY(launch_dslash_dmu(lat, out_parity, nrhs, nder, lk, vin, vout, s));
         return HISQ_OK;
@@ -1325,7 +1330,7 @@ int hisq_dslash_dmu(const hisq_geom* g, int out_parity, int nrhs, int nder, cons
     a.links = lk;
     a.in = vin;
     a.out = vout;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, false, default_tile(nrhs, HISQ_PREC_F64), a, s, false));
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, default_tile(nrhs, HISQ_PREC_F64), a, s, false));
     return HISQ_OK;
 }
 
@@ -1421,7 +1426,7 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
     Engine E;
     E.prm = *p;
     E.mixed = p->mode == HISQ_MODE_MIXED;
-    E.r14 = E.mixed && p->naik == HISQ_NAIK_R14;
+    E.nk = E.mixed ? p->naik : HISQ_NAIK_FULL;
     E.s = reinterpret_cast<hipStream_t>(stream);
     E.states = states;
     E.table = table;

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_dslash_dmu(Lat lat, int parity, const d
     auto slot = [&](auto S, double w) {
         constexpr int s = decltype(S)::value;
         d2 m[9];
-        load_link<double, false, s>(lk, lat.Vh, i, m);
+        load_link<double, HISQ_NAIK_FULL, s>(lk, lat.Vh, i, m);
         const int nb = neighbour<s>(lat, sc);
 #pragma unroll
         for (int e = 0; e < 9; ++e) m[e] = d2{w * m[e].x, w * m[e].y};

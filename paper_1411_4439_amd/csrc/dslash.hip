@@ -10,7 +10,8 @@
 // dot products are accumulated in FP64.
 //
 // This file is compiled once per (precision, Naik storage, epilogue):
-//   HISQ_KPREC 0 = FP64, 1 = FP32, 2 = FP32 with r14 Naik links
+//   HISQ_KPREC 0 = FP64, 1 = FP32, 2 = FP32 with r14 Naik links,
+//              3 = FP32 with r13 Naik links
 //   HISQ_KEPI  one of EPI_PLAIN, EPI_NORM, EPI_CG, EPI_RESID
 #include <type_traits>
 
@@ -27,13 +28,16 @@ namespace hisq {
 
 #if HISQ_KPREC == 0
 using KT = double;
-constexpr bool kR14 = false;
+constexpr int kNK = HISQ_NAIK_FULL;
 #elif HISQ_KPREC == 1
 using KT = float;
-constexpr bool kR14 = false;
+constexpr int kNK = HISQ_NAIK_FULL;
+#elif HISQ_KPREC == 2
+using KT = float;
+constexpr int kNK = HISQ_NAIK_R14;
 #else
 using KT = float;
-constexpr bool kR14 = true;
+constexpr int kNK = HISQ_NAIK_R13;
 #endif
 
 template <typename T, int NRHS, int NR, bool CM>
@@ -46,13 +50,53 @@ __device__ __forceinline__ void load_vec(const cplx<T>* __restrict__ in, int Vh,
     for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + Lay::colour(b, Vh), v[b]);
 }
 
-template <typename T, int NR, bool R14, int S>
+// exp(i phi) for phi in [-pi, pi] (the packer stores atan2's result): Taylor
+// series of sin and cos at phi/2 in [-pi/2, pi/2] (truncation below 6e-8),
+// then the double-angle formulas; within 4e-7 of the exact value in FP32.
+// A library sincosf inlines a large-argument reduction that costs this kernel
+// its registers.
+__device__ __forceinline__ void unit_phase(float phi, float* cs, float* sn)
+{
+    const float t = 0.5f * phi, t2 = t * t;
+    float s = 1.0f - t2 * (1.0f / (12 * 13));
+    s = 1.0f - t2 * (1.0f / (10 * 11)) * s;
+    s = 1.0f - t2 * (1.0f / (8 * 9)) * s;
+    s = 1.0f - t2 * (1.0f / (6 * 7)) * s;
+    s = 1.0f - t2 * (1.0f / (4 * 5)) * s;
+    s = t * (1.0f - t2 * (1.0f / (2 * 3)) * s);
+    float c = 1.0f - t2 * (1.0f / (13 * 14));
+    c = 1.0f - t2 * (1.0f / (11 * 12)) * c;
+    c = 1.0f - t2 * (1.0f / (9 * 10)) * c;
+    c = 1.0f - t2 * (1.0f / (7 * 8)) * c;
+    c = 1.0f - t2 * (1.0f / (5 * 6)) * c;
+    c = 1.0f - t2 * (1.0f / (3 * 4)) * c;
+    c = 1.0f - t2 * (1.0f / (1 * 2)) * c;
+    *cs = c * c - s * s;
+    *sn = 2.0f * s * c;
+}
+
+// Naik storage r13: c = exp(i phi) / |row0|, phi loaded into m[6].x (for
+// N = s V, V in U(3): |row0| = s and c = det V / s)
+template <typename T>
+__device__ __forceinline__ cplx<T> r13_coefficient(const cplx<T> (&m)[9])
+{
+    static_assert(sizeof(T) == 4, "r13 is an FP32 storage");
+    const float n2 = m[0].x * m[0].x + m[0].y * m[0].y + m[1].x * m[1].x + m[1].y * m[1].y +
+                     m[2].x * m[2].x + m[2].y * m[2].y;
+    float cs, sn;
+    unit_phase(m[6].x, &cs, &sn);
+    const float inv = __builtin_amdgcn_rsqf(n2);
+    return cplx<T>{cs * inv, sn * inv};
+}
+
+template <typename T, int NR, int NK, int S>
 __device__ __forceinline__ void apply_slot(cplx<T> (&m)[9], const cplx<T> (&v)[3][NR],
                                            cplx<T> (&acc)[3][NR])
 {
-    if constexpr (R14 && S >= 8) {
-        // row 2 = c * conj(row0 x row1); c was loaded into m[6]
-        const cplx<T> cc = m[6];
+    if constexpr (NK != HISQ_NAIK_FULL && S >= 8) {
+        // row 2 = c * conj(row0 x row1); r14 loaded c into m[6], r13 its phase
+        cplx<T> cc = m[6];
+        if constexpr (NK == HISQ_NAIK_R13) cc = r13_coefficient<T>(m);
         m[6] = cmul(cc, cconj(cmul(m[1], m[5]) - cmul(m[2], m[4])));
         m[7] = cmul(cc, cconj(cmul(m[2], m[3]) - cmul(m[0], m[5])));
         m[8] = cmul(cc, cconj(cmul(m[0], m[4]) - cmul(m[1], m[3])));
@@ -83,7 +127,7 @@ __host__ __device__ constexpr int slot_at(int k)
 // the longest latency; neighbour vectors mostly hit L2).  The scheduling
 // barriers keep the compiler from hoisting further loads, which would
 // otherwise exhaust the register file.
-template <typename T, int NRHS, int NR, bool R14, bool CM>
+template <typename T, int NRHS, int NR, int NK, bool CM>
 __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
                                             const cplx<T>* __restrict__ lk,
                                             const cplx<T>* __restrict__ in,
@@ -105,17 +149,17 @@ __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
     constexpr int LD = sizeof(T) == 4 ? HISQ_FP32_LINK_LOOKAHEAD : 1;
     C m[LD + 1][9];
     C v[2][3][NR];
-    load_link<T, R14, slot_at(0)>(lk, Vh, i, m[0]);
-    if constexpr (LD == 2) load_link<T, R14, slot_at(1)>(lk, Vh, i, m[1]);
+    load_link<T, NK, slot_at(0)>(lk, Vh, i, m[0]);
+    if constexpr (LD == 2) load_link<T, NK, slot_at(1)>(lk, Vh, i, m[1]);
     load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(0)>(lat, sc), g, v[0]);
     static_for<0, 16>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (k + LD < 16)
-            load_link<T, R14, slot_at(k + LD)>(lk, Vh, i, m[(k + LD) % (LD + 1)]);
+            load_link<T, NK, slot_at(k + LD)>(lk, Vh, i, m[(k + LD) % (LD + 1)]);
         if constexpr (k + 1 < 16)
             load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(k + 1)>(lat, sc), g, v[(k + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
-        apply_slot<T, NR, R14, slot_at(k)>(m[k % (LD + 1)], v[k & 1], acc);
+        apply_slot<T, NR, NK, slot_at(k)>(m[k % (LD + 1)], v[k & 1], acc);
         __builtin_amdgcn_sched_barrier(0);
     });
 }
@@ -196,7 +240,7 @@ __device__ __forceinline__ int lds_neighbour(const Lat& lat, int r, int xh, int 
 // read issued before it: an even (global) step issues the next link, computes,
 // then issues the link after that and the global neighbour of four steps ahead
 // (two global slots of lookahead), and the LDS neighbour of the next step.
-template <typename T, int NRHS, int NR, bool R14>
+template <typename T, int NRHS, int NR, int NK>
 __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, int g, int r,
                                                 const cplx<T>* __restrict__ lk,
                                                 const cplx<T>* __restrict__ in,
@@ -215,24 +259,24 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
     C m[2][9];
     C vg[2][3][NR];
     C vl[3][NR];
-    load_link<T, R14, slot_at(0)>(lk, Vh, i, m[0]);
+    load_link<T, NK, slot_at(0)>(lk, Vh, i, m[0]);
     load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(0)>(lat, sc), g, vg[0]);
     load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(2)>(lat, sc), g, vg[1]);
     static_for<0, 16>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (k % 2 == 0) {
-            load_link<T, R14, slot_at(k + 1)>(lk, Vh, i, m[(k + 1) & 1]);
+            load_link<T, NK, slot_at(k + 1)>(lk, Vh, i, m[(k + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
-            apply_slot<T, NR, R14, slot_at(k)>(m[k & 1], vg[(k >> 1) & 1], acc);
+            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vg[(k >> 1) & 1], acc);
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (k + 2 < 16) load_link<T, R14, slot_at(k + 2)>(lk, Vh, i, m[k & 1]);
+            if constexpr (k + 2 < 16) load_link<T, NK, slot_at(k + 2)>(lk, Vh, i, m[k & 1]);
             if constexpr (k + 4 < 16)
                 load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(k + 4)>(lat, sc), g,
                                             vg[(k >> 1) & 1]);
             load_vec_lds<T, NRHS, NR>(lds, cstride,
                                       lds_neighbour<slot_at(k + 1)>(lat, r, xh, sc.x), g, vl);
         } else {
-            apply_slot<T, NR, R14, slot_at(k)>(m[k & 1], vl, acc);
+            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vl, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
     });
@@ -295,7 +339,7 @@ __device__ __forceinline__ double norm2c(cplx<T> v)
 // One tile (one work-group's worth of sites) of a half-Dslash with epilogue
 // EPI; `tile` is the tile index, the problem's grid has nblk work-groups and
 // this one is number bid (for the reductions).
-template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM, bool ST = false>
+template <typename T, int NRHS, int NR, int NK, int EPI, bool CM, bool ST = false>
 __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, int nblk, int bid,
                                             cplx<T>* lds = nullptr)
 {
@@ -340,11 +384,11 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
     if (i < a.lat.Vh) {
         C acc[3][NR];
         if constexpr (ST)
-            dslash_site_lds<T, NRHS, NR, R14>(a.lat, a.parity, i, g,
+            dslash_site_lds<T, NRHS, NR, NK>(a.lat, a.parity, i, g,
                                               ((int)threadIdx.x / G) / a.lat.Lh0, a.links, a.in,
                                               lds, a.rows + 6, acc);
         else
-            dslash_site<T, NRHS, NR, R14, CM>(a.lat, a.parity, i, g, a.links, a.in, acc);
+            dslash_site<T, NRHS, NR, NK, CM>(a.lat, a.parity, i, g, a.links, a.in, acc);
         pin_acc(acc);
         using Lay = Layout<NRHS, CM>;
         const int base = Lay::site(i) + g * NR;
@@ -413,20 +457,20 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 #define HISQ_KATTR
 #endif
 
-template <typename T, int NRHS, int NR, bool R14, int EPI, bool CM>
+template <typename T, int NRHS, int NR, int NK, int EPI, bool CM>
 __global__ __launch_bounds__(kMaxBlock) HISQ_KATTR void k_dslash(const DslashArgs<T> a)
 {
     const int tile_sites = (int)blockDim.x / (NRHS / NR);
-    dslash_tile<T, NRHS, NR, R14, EPI, CM>(
+    dslash_tile<T, NRHS, NR, NK, EPI, CM>(
         a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat, tile_sites), gridDim.x, blockIdx.x);
 }
 
-template <typename T, int NRHS, int NR, bool R14, int EPI>
+template <typename T, int NRHS, int NR, int NK, int EPI>
 __global__ __launch_bounds__(kMaxBlockLds) void k_dslash_lds(const DslashArgs<T> a)
 {
     extern __shared__ __align__(16) unsigned char hisq_stage[];
     const int tile_sites = (int)blockDim.x / (NRHS / NR);
-    dslash_tile<T, NRHS, NR, R14, EPI, true, true>(
+    dslash_tile<T, NRHS, NR, NK, EPI, true, true>(
         a, tile_of_block(blockIdx.x, gridDim.x, a.remap, a.lat, tile_sites), gridDim.x, blockIdx.x,
         reinterpret_cast<cplx<T>*>(hisq_stage));
 }
@@ -434,7 +478,7 @@ __global__ __launch_bounds__(kMaxBlockLds) void k_dslash_lds(const DslashArgs<T>
 // Batched form: one launch covers the tiles of every problem of a BatchTable;
 // each work-group finds its problem (uniform scalar search over <= 16 entries)
 // and runs the body specialised for that problem's bundle size and tile.
-template <typename T, bool R14, int EPI>
+template <typename T, int NK, int EPI>
 __global__ __launch_bounds__(kMaxBlock) void k_dslash_batched(const BatchTable<T>* __restrict__ tab)
 {
     int q = 0;
@@ -446,23 +490,23 @@ __global__ __launch_bounds__(kMaxBlock) void k_dslash_batched(const BatchTable<T
     const DslashArgs<T>& a = EPI == EPI_NORM ? bp.k2 : bp.k3;
     const int nb = bp.nblocks;
     switch (bp.n * 16 + bp.nr) {
-    case 1 * 16 + 1: dslash_tile<T, 1, 1, R14, EPI, true>(a, bid, nb, bid); break;
-    case 2 * 16 + 2: dslash_tile<T, 2, 2, R14, EPI, true>(a, bid, nb, bid); break;
-    case 2 * 16 + 1: dslash_tile<T, 2, 1, R14, EPI, true>(a, bid, nb, bid); break;
-    case 3 * 16 + 3: dslash_tile<T, 3, 3, R14, EPI, true>(a, bid, nb, bid); break;
-    case 4 * 16 + 4: dslash_tile<T, 4, 4, R14, EPI, true>(a, bid, nb, bid); break;
-    case 4 * 16 + 2: dslash_tile<T, 4, 2, R14, EPI, true>(a, bid, nb, bid); break;
-    case 5 * 16 + 5: dslash_tile<T, 5, 5, R14, EPI, true>(a, bid, nb, bid); break;
-    case 6 * 16 + 6: dslash_tile<T, 6, 6, R14, EPI, true>(a, bid, nb, bid); break;
-    case 6 * 16 + 3: dslash_tile<T, 6, 3, R14, EPI, true>(a, bid, nb, bid); break;
-    case 7 * 16 + 7: dslash_tile<T, 7, 7, R14, EPI, true>(a, bid, nb, bid); break;
-    case 8 * 16 + 8: dslash_tile<T, 8, 8, R14, EPI, true>(a, bid, nb, bid); break;
-    case 8 * 16 + 4: dslash_tile<T, 8, 4, R14, EPI, true>(a, bid, nb, bid); break;
+    case 1 * 16 + 1: dslash_tile<T, 1, 1, NK, EPI, true>(a, bid, nb, bid); break;
+    case 2 * 16 + 2: dslash_tile<T, 2, 2, NK, EPI, true>(a, bid, nb, bid); break;
+    case 2 * 16 + 1: dslash_tile<T, 2, 1, NK, EPI, true>(a, bid, nb, bid); break;
+    case 3 * 16 + 3: dslash_tile<T, 3, 3, NK, EPI, true>(a, bid, nb, bid); break;
+    case 4 * 16 + 4: dslash_tile<T, 4, 4, NK, EPI, true>(a, bid, nb, bid); break;
+    case 4 * 16 + 2: dslash_tile<T, 4, 2, NK, EPI, true>(a, bid, nb, bid); break;
+    case 5 * 16 + 5: dslash_tile<T, 5, 5, NK, EPI, true>(a, bid, nb, bid); break;
+    case 6 * 16 + 6: dslash_tile<T, 6, 6, NK, EPI, true>(a, bid, nb, bid); break;
+    case 6 * 16 + 3: dslash_tile<T, 6, 3, NK, EPI, true>(a, bid, nb, bid); break;
+    case 7 * 16 + 7: dslash_tile<T, 7, 7, NK, EPI, true>(a, bid, nb, bid); break;
+    case 8 * 16 + 8: dslash_tile<T, 8, 8, NK, EPI, true>(a, bid, nb, bid); break;
+    case 8 * 16 + 4: dslash_tile<T, 8, 4, NK, EPI, true>(a, bid, nb, bid); break;
     default: break;
     }
 }
 
-template <typename T, bool R14, int EPI, int NRHS, int NR>
+template <typename T, int NK, int EPI, int NRHS, int NR>
 static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s, bool cm)
 {
     constexpr int G = NRHS / NR;
@@ -475,29 +519,29 @@ static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s, bool cm)
         // t.rows whole x-rows of one plane and that the rows fit in LDS
         if (!cm) return hipErrorInvalidValue;
         const size_t lds = (size_t)3 * (t.rows + 6) * a.lat.Lh0 * NRHS * sizeof(cplx<T>);
-        hipLaunchKernelGGL((k_dslash_lds<T, NRHS, NR, R14, EPI>), dim3(a.ntiles), dim3(t.bs), lds, s, a);
+        hipLaunchKernelGGL((k_dslash_lds<T, NRHS, NR, NK, EPI>), dim3(a.ntiles), dim3(t.bs), lds, s, a);
         return hipGetLastError();
     }
     // the solver's kernels exist in colour-major form only; the plain Dslash in both
     if (cm)
-        hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI, true>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
+        hipLaunchKernelGGL((k_dslash<T, NRHS, NR, NK, EPI, true>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
     else if constexpr (EPI == EPI_PLAIN)
-        hipLaunchKernelGGL((k_dslash<T, NRHS, NR, R14, EPI, false>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
+        hipLaunchKernelGGL((k_dslash<T, NRHS, NR, NK, EPI, false>), dim3(a.ntiles), dim3(t.bs), 0, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-template <typename T, bool R14, int EPI, int NRHS>
+template <typename T, int NK, int EPI, int NRHS>
 static hipError_t pick_nr(const Tile& t, const DslashArgs<T>& a, hipStream_t s, bool cm)
 {
-    if (t.nr == NRHS) return go<T, R14, EPI, NRHS, NRHS>(t, a, s, cm);
+    if (t.nr == NRHS) return go<T, NK, EPI, NRHS, NRHS>(t, a, s, cm);
     if constexpr (NRHS % 2 == 0)
-        if (t.nr == NRHS / 2) return go<T, R14, EPI, NRHS, NRHS / 2>(t, a, s, cm);
+        if (t.nr == NRHS / 2) return go<T, NK, EPI, NRHS, NRHS / 2>(t, a, s, cm);
     if constexpr (NRHS % 4 == 0)
-        if (t.nr == NRHS / 4) return go<T, R14, EPI, NRHS, NRHS / 4>(t, a, s, cm);
+        if (t.nr == NRHS / 4) return go<T, NK, EPI, NRHS, NRHS / 4>(t, a, s, cm);
     if constexpr (NRHS % 8 == 0)
-        if (t.nr == NRHS / 8) return go<T, R14, EPI, NRHS, NRHS / 8>(t, a, s, cm);
+        if (t.nr == NRHS / 8) return go<T, NK, EPI, NRHS, NRHS / 8>(t, a, s, cm);
     return hipErrorInvalidValue;
 }
 
@@ -512,14 +556,14 @@ hipError_t HISQ_LAUNCH_NAME(int nrhs, const Tile& t, const DslashArgs<KT>& a, hi
         return hipErrorInvalidValue;
     } else {
         switch (nrhs) {
-        case 1: return pick_nr<KT, kR14, EPI, 1>(t, a, s, cm);
-        case 2: return pick_nr<KT, kR14, EPI, 2>(t, a, s, cm);
-        case 3: return pick_nr<KT, kR14, EPI, 3>(t, a, s, cm);
-        case 4: return pick_nr<KT, kR14, EPI, 4>(t, a, s, cm);
-        case 5: return pick_nr<KT, kR14, EPI, 5>(t, a, s, cm);
-        case 6: return pick_nr<KT, kR14, EPI, 6>(t, a, s, cm);
-        case 7: return pick_nr<KT, kR14, EPI, 7>(t, a, s, cm);
-        case 8: return pick_nr<KT, kR14, EPI, 8>(t, a, s, cm);
+        case 1: return pick_nr<KT, kNK, EPI, 1>(t, a, s, cm);
+        case 2: return pick_nr<KT, kNK, EPI, 2>(t, a, s, cm);
+        case 3: return pick_nr<KT, kNK, EPI, 3>(t, a, s, cm);
+        case 4: return pick_nr<KT, kNK, EPI, 4>(t, a, s, cm);
+        case 5: return pick_nr<KT, kNK, EPI, 5>(t, a, s, cm);
+        case 6: return pick_nr<KT, kNK, EPI, 6>(t, a, s, cm);
+        case 7: return pick_nr<KT, kNK, EPI, 7>(t, a, s, cm);
+        case 8: return pick_nr<KT, kNK, EPI, 8>(t, a, s, cm);
         default: return hipErrorInvalidValue;
         }
     }
@@ -529,7 +573,7 @@ hipError_t HISQ_LAUNCH_NAME(int nrhs, const Tile& t, const DslashArgs<KT>& a, hi
 #define HISQ_BNAME HISQ_CAT(HISQ_CAT(HISQ_CAT(launch_dslash_batched_p, HISQ_KPREC), _e), HISQ_KEPI)
 hipError_t HISQ_BNAME(const BatchTable<KT>* tab, int total_blocks, int bs, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_dslash_batched<KT, kR14, HISQ_KEPI>), dim3(total_blocks), dim3(bs), 0, s,
+    hipLaunchKernelGGL((k_dslash_batched<KT, kNK, HISQ_KEPI>), dim3(total_blocks), dim3(bs), 0, s,
                        tab);
     return hipGetLastError();
 }

@@ -55,14 +55,14 @@ constexpr int kMaxBlock = 256;
 // neighbour rows.
 constexpr int kMaxBlockLds = 512;
 constexpr int kMaxStageBytes = 64 * 1024;
-constexpr float kR14Tolerance = 1e-6f;
+constexpr float kNaikTolerance = 1e-6f;  // r14 / r13 round-trip error bound
 
 struct LinkHeader {
     uint32_t magic;
     int32_t L[4];
     int32_t prec;
     int32_t naik;
-    uint32_t r14_err_bits;  // max relative round-trip error, float bits (atomicMax)
+    uint32_t naik_err_bits;  // r14 / r13: max relative round-trip error, float bits (atomicMax)
 };
 
 // Lattice description as the kernels see it.
@@ -85,29 +85,38 @@ inline Lat make_lat(const hisq_geom& g)
     return l;
 }
 
-// Complex elements in the link block of one output parity.
-__host__ __device__ inline size_t link_block_elems(int Vh, bool r14)
+// Packed link block of one output parity: 16 slots (U fwd, -U^dag bwd, N fwd,
+// -N^dag bwd per direction), each one matrix per site.  Sizes in reals (float or
+// double).  U slots hold 18 reals; a Naik slot holds 18 (FULL), 14 (R14: rows 0
+// and 1 and one complex c with row2 = c conj(row0 x row1)) or 13 (R13: rows 0
+// and 1 and the phase phi of c = exp(i phi) / |row0|).  R14 and R13 are FP32.
+__host__ __device__ constexpr int naik_reals(int nk)
 {
-    return size_t(r14 ? 8 * 9 + 8 * 7 : 16 * 9) * size_t(Vh);
+    return nk == HISQ_NAIK_R14 ? 14 : nk == HISQ_NAIK_R13 ? 13 : 18;
 }
 
-__host__ __device__ constexpr int link_slot_elem(int slot, bool r14)
+__host__ __device__ constexpr int slot_reals(int slot, int nk) { return slot < 8 ? 18 : naik_reals(nk); }
+
+__host__ __device__ constexpr int slot_real_start(int slot, int nk)
 {
-    return slot < 8 ? 9 * slot : 72 + (r14 ? 7 : 9) * (slot - 8);
+    return slot < 8 ? 18 * slot : 144 + naik_reals(nk) * (slot - 8);
 }
 
-// Position of element e (0 <= e < ne, ne = 9, or 7 for an r14 Naik slot) of
-// site i's matrix, in complex numbers from the slot's start.  FP64: [e][Vh].
-// FP32: elements pair up into 16-byte words, [e/2][Vh][2], so that one load
-// brings two of them; the odd last element has a plane [Vh] of its own after
-// the words.  Same bytes either way.
-template <typename T>
-__host__ __device__ inline size_t link_elem_offset(int e, int ne, int Vh, int i)
+__host__ __device__ inline size_t link_block_reals(int Vh, int nk)
 {
-    if (sizeof(T) == 8) return (size_t)e * Vh + i;
-    const int nw = ne / 2;
-    if (e < 2 * nw) return ((size_t)(e >> 1) * Vh + i) * 2 + (e & 1);
-    return (size_t)2 * nw * Vh + i;
+    return size_t(144 + 8 * naik_reals(nk)) * size_t(Vh);
+}
+
+// FP32: position (in floats, from the slot's start) of real r (0 <= r < nr) of
+// site i's matrix.  Reals group into 16-byte words, [r/4][Vh][4], so that one
+// load brings two complex numbers; the nr % 4 remaining reals follow as a plane
+// [Vh][nr % 4].  FP64 slots are [element][Vh] complex.  Slot starts stay 16-byte
+// aligned because Vh is a multiple of 8.
+__host__ __device__ inline size_t slot_real_offset32(int r, int nr, int Vh, int i)
+{
+    const int nw = nr / 4, rem = nr % 4;
+    if (r < 4 * nw) return ((size_t)(r >> 2) * Vh + i) * 4 + (r & 3);
+    return (size_t)4 * nw * Vh + (size_t)i * rem + (r - 4 * nw);
 }
 
 // Per-problem CG scalars, in device memory (FP64).
@@ -210,13 +219,12 @@ inline size_t red_counters(size_t blocks) { return 1 + (blocks + 63) / 64; }
 // exists for the site-major canonical layout [Vh][3][n].
 hipError_t launch_dslash_f64(int epi, int nrhs, const Tile& t, const DslashArgs<double>& a,
                              hipStream_t s, bool cm);
-hipError_t launch_dslash_f32(int epi, int nrhs, const Tile& t, const DslashArgs<float>& a,
+// nk: Naik storage of the FP32 links (HISQ_NAIK_FULL, _R14, _R13)
+hipError_t launch_dslash_f32(int epi, int nk, int nrhs, const Tile& t, const DslashArgs<float>& a,
                              hipStream_t s, bool cm);
-hipError_t launch_dslash_f32r14(int epi, int nrhs, const Tile& t, const DslashArgs<float>& a,
-                                hipStream_t s, bool cm);
 hipError_t launch_dslash_batched_f64(int epi, const BatchTable<double>* tab, int total_blocks,
                                      int bs, hipStream_t s);
-hipError_t launch_dslash_batched_f32(int epi, bool r14, const BatchTable<float>* tab,
+hipError_t launch_dslash_batched_f32(int epi, int nk, const BatchTable<float>* tab,
                                      int total_blocks, int bs, hipStream_t s);
 hipError_t launch_pupdate_batched_f64(const BatchTable<double>* tab, int total_blocks, int bs,
                                       hipStream_t s);

@@ -22,9 +22,9 @@ __device__ __forceinline__ int site_of(const Lat& lat, const int x[4])
     return x[0] + lat.L[0] * (x[1] + lat.L[1] * (x[2] + lat.L[2] * x[3]));
 }
 
-template <typename T, bool R14>
+template <typename T, int NK>
 __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__ N,
-                       cplx<T>* __restrict__ out, LinkHeader* hdr)
+                       T* __restrict__ out, LinkHeader* hdr)
 {
     using C = cplx<T>;
     const int Vh = lat.Vh;
@@ -42,7 +42,14 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
     c[3] = r / lat.L[2];
     c[0] = 2 * xh + ((P + c[1] + c[2] + c[3]) & 1);
     const int s = site_of(lat, c);
-    C* blk = out + (size_t)P * link_block_elems(Vh, R14);
+    T* blk = out + (size_t)P * link_block_reals(Vh, NK);
+    // real r of site i's matrix in a slot of nr reals
+    auto put = [&](T* slot, int nr, int r, T v) {
+        if constexpr (sizeof(T) == 4)
+            slot[slot_real_offset32(r, nr, Vh, i)] = v;
+        else
+            slot[((size_t)(r >> 1) * Vh + i) * 2 + (r & 1)] = v;
+    };
     float worst = 0.0f;
     for (int slot = 0; slot < 16; ++slot) {
         const int mu = slot & 3, kind = slot >> 2;  // 0: U fwd, 1: U bwd, 2: N fwd, 3: N bwd
@@ -63,8 +70,9 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
                 for (int b = 0; b < 3; ++b) t[3 * a + b] = d2{-m[3 * b + a].x, m[3 * b + a].y};
             for (int e = 0; e < 9; ++e) m[e] = t[e];
         }
-        C* dst = blk + (size_t)link_slot_elem(slot, R14) * Vh;
-        if (R14 && slot >= 8) {
+        T* dst = blk + (size_t)slot_real_start(slot, NK) * Vh;
+        const int nr = slot_reals(slot, NK);
+        if (NK != HISQ_NAIK_FULL && slot >= 8) {
             // w = conj(row0 x row1); c = <w, row2> / |w|^2
             d2 w[3];
             w[0] = cmul_d(m[1], m[5]) - cmul_d(m[2], m[4]);
@@ -77,7 +85,14 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
                 num += cmul_d(d2{w[j].x, -w[j].y}, m[6 + j]);
                 den += w[j].x * w[j].x + w[j].y * w[j].y;
             }
-            const d2 cc = den > 0 ? d2{num.x / den, num.y / den} : d2{0, 0};
+            d2 cc = den > 0 ? d2{num.x / den, num.y / den} : d2{0, 0};
+            const double phi = atan2(cc.y, cc.x);
+            if (NK == HISQ_NAIK_R13) {
+                // r13 keeps only the phase; the modulus is 1 / |row0|
+                const double r0 = sqrt(m[0].x * m[0].x + m[0].y * m[0].y + m[1].x * m[1].x +
+                                       m[1].y * m[1].y + m[2].x * m[2].x + m[2].y * m[2].y);
+                cc = r0 > 0 ? d2{cos(phi) / r0, sin(phi) / r0} : d2{0, 0};
+            }
             for (int e = 0; e < 9; ++e) fro += m[e].x * m[e].x + m[e].y * m[e].y;
             for (int j = 0; j < 3; ++j) {
                 const d2 d = m[6 + j] - cmul_d(cc, w[j]);
@@ -86,13 +101,24 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
             const double rel = fro > 0 ? sqrt(err / fro) : 0.0;
             const float relf = (rel == rel) ? (float)rel : 3.0e38f;
             worst = fmaxf(worst, relf);
-            for (int e = 0; e < 6; ++e) dst[link_elem_offset<T>(e, 7, Vh, i)] = C{(T)m[e].x, (T)m[e].y};
-            dst[link_elem_offset<T>(6, 7, Vh, i)] = C{(T)cc.x, (T)cc.y};
+            for (int e = 0; e < 6; ++e) {
+                put(dst, nr, 2 * e, (T)m[e].x);
+                put(dst, nr, 2 * e + 1, (T)m[e].y);
+            }
+            if (NK == HISQ_NAIK_R14) {
+                put(dst, nr, 12, (T)cc.x);
+                put(dst, nr, 13, (T)cc.y);
+            } else {
+                put(dst, nr, 12, (T)phi);
+            }
         } else {
-            for (int e = 0; e < 9; ++e) dst[link_elem_offset<T>(e, 9, Vh, i)] = C{(T)m[e].x, (T)m[e].y};
+            for (int e = 0; e < 9; ++e) {
+                put(dst, nr, 2 * e, (T)m[e].x);
+                put(dst, nr, 2 * e + 1, (T)m[e].y);
+            }
         }
     }
-    if (R14 && worst > 0.0f) atomicMax(&hdr->r14_err_bits, __float_as_uint(worst));
+    if (NK != HISQ_NAIK_FULL && worst > 0.0f) atomicMax(&hdr->naik_err_bits, __float_as_uint(worst));
 }
 
 __global__ void k_pack_header(LinkHeader h, LinkHeader* dst) { *dst = h; }
@@ -105,7 +131,7 @@ hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int n
     for (int mu = 0; mu < 4; ++mu) h.L[mu] = lat.L[mu];
     h.prec = prec;
     h.naik = naik;
-    h.r14_err_bits = 0u;
+    h.naik_err_bits = 0u;
     LinkHeader* hdr = reinterpret_cast<LinkHeader*>(packed);
     hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, s, h, hdr);
     hipError_t e = hipGetLastError();
@@ -113,14 +139,17 @@ hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int n
     char* body = reinterpret_cast<char*>(packed) + kLinkHeaderBytes;
     const int V = 2 * lat.Vh, bs = 128, grid = (V + bs - 1) / bs;
     if (prec == HISQ_PREC_F64)
-        hipLaunchKernelGGL((k_pack<double, false>), dim3(grid), dim3(bs), 0, s, lat, U, N,
-                           reinterpret_cast<d2*>(body), hdr);
+        hipLaunchKernelGGL((k_pack<double, HISQ_NAIK_FULL>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<double*>(body), hdr);
     else if (naik == HISQ_NAIK_R14)
-        hipLaunchKernelGGL((k_pack<float, true>), dim3(grid), dim3(bs), 0, s, lat, U, N,
-                           reinterpret_cast<f2*>(body), hdr);
+        hipLaunchKernelGGL((k_pack<float, HISQ_NAIK_R14>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<float*>(body), hdr);
+    else if (naik == HISQ_NAIK_R13)
+        hipLaunchKernelGGL((k_pack<float, HISQ_NAIK_R13>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<float*>(body), hdr);
     else
-        hipLaunchKernelGGL((k_pack<float, false>), dim3(grid), dim3(bs), 0, s, lat, U, N,
-                           reinterpret_cast<f2*>(body), hdr);
+        hipLaunchKernelGGL((k_pack<float, HISQ_NAIK_FULL>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<float*>(body), hdr);
     return hipGetLastError();
 }
 

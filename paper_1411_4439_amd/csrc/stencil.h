@@ -51,29 +51,38 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-// Link matrix of slot S for site i into m[0..ne-1] (ne = 9, or 7 for an r14
-// Naik slot), non-temporal (no reuse within a half-Dslash).  FP32 reads 16-byte
-// words of two elements: the same bytes in fewer, wider requests, which is
-// measurably faster than one 8-byte read per element.
-template <typename T, bool R14, int S>
+// Link matrix of slot S for site i, non-temporal (no reuse within a
+// half-Dslash).  m[e] holds element e of the 3x3 matrix, row-major; for a
+// compressed Naik slot (NK = R14, R13) m[0..5] hold rows 0 and 1 and m[6] the
+// stored coefficient (r14: c; r13: its phase in m[6].x).  FP32 reads 16-byte
+// words of four reals, then the remaining 1 or 2 reals: the same bytes in
+// fewer, wider requests than one 8-byte read per element.
+template <typename T, int NK, int S>
 __device__ __forceinline__ void load_link(const cplx<T>* __restrict__ lk, int Vh, int i,
                                           cplx<T> (&m)[9])
 {
-    const cplx<T>* lp = lk + link_slot_elem(S, R14) * Vh;
-    constexpr int ne = (R14 && S >= 8) ? 7 : 9;
+    const T* base = reinterpret_cast<const T*>(lk) + (size_t)slot_real_start(S, NK) * Vh;
     if constexpr (sizeof(T) == 4) {
-        constexpr int nw = ne / 2;
-        const f4* wp = reinterpret_cast<const f4*>(lp) + i;
+        constexpr int nr = slot_reals(S, NK);
+        constexpr int nw = nr / 4, rem = nr % 4;
+        const f4* wp = reinterpret_cast<const f4*>(base) + i;
 #pragma unroll
         for (int w = 0; w < nw; ++w) {
             const f4 q = __builtin_nontemporal_load(wp + (size_t)w * Vh);
             m[2 * w] = cplx<T>{q.x, q.y};
             m[2 * w + 1] = cplx<T>{q.z, q.w};
         }
-        m[ne - 1] = __builtin_nontemporal_load(lp + (size_t)2 * nw * Vh + i);
+        const T* tail = base + (size_t)4 * nw * Vh;
+        if constexpr (rem == 2) {
+            m[2 * nw] = __builtin_nontemporal_load(reinterpret_cast<const cplx<T>*>(tail) + i);
+        } else if constexpr (rem == 1) {
+            m[2 * nw] = cplx<T>{__builtin_nontemporal_load(tail + i), T(0)};
+        }
     } else {
+        static_assert(NK == HISQ_NAIK_FULL, "FP64 links are stored in full");
+        const cplx<T>* lp = reinterpret_cast<const cplx<T>*>(base) + i;
 #pragma unroll
-        for (int e = 0; e < ne; ++e) m[e] = __builtin_nontemporal_load(lp + (size_t)e * Vh + i);
+        for (int e = 0; e < 9; ++e) m[e] = __builtin_nontemporal_load(lp + (size_t)e * Vh);
     }
 }
 

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 def _setup(H, L, eps, seed, n, sseed):
     U, N = W.make_links(L, eps, seed)
-    links = H.Links(L, dev(U), dev(N))
+    links = H.Links(L, dev(U), dev(N), r13=True)
     b = W.make_sources(L, n, sseed)
     return U, N, links, b
 
@@ -47,7 +47,8 @@ def test_config1_fp64_8x4():
     assert abs(info["iters"][0] - o10["iters"][0]) <= 0.05 * o10["iters"][0] + 3
 
 
-@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14")])
+@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14"),
+                                       ("mixed", "r13")])
 @pytest.mark.parametrize("n", [1, 3, 4, 8])
 def test_bundles_vs_lapack(mode, naik, n):
     """4^4 (wrap aliasing): every rhs against LAPACK's dense solve."""
@@ -55,7 +56,7 @@ def test_bundles_vs_lapack(mode, naik, n):
     L, m = (4, 4, 4, 4), 0.05
     U, N, links, b = _setup(H, L, 0.3, 21, n, 22 + n)
     md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
-    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_FULL
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13}.get(naik, H.NAIK_FULL)
     x, status, info = H.solve(links, m, dev(b), mode=md, naik=nk)
     say(mode, naik, n, info["iters"], info["reliable_updates"])
     assert status == H.HISQ_OK
@@ -66,14 +67,15 @@ def test_bundles_vs_lapack(mode, naik, n):
         assert info["reliable_updates"] >= 1
 
 
-@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14")])
+@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14"),
+                                       ("mixed", "r13")])
 def test_medium_lattice_small_mass(mode, naik):
     """16^3 x 4 (ragged tiles in every tile shape), m = 0.01, n = 5."""
     H = gpu_lib()
     L, m, n = (16, 16, 16, 4), 0.01, 5
     U, N, links, b = _setup(H, L, 0.3, 31, n, 32)
     md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
-    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_FULL
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13}.get(naik, H.NAIK_FULL)
     x, status, info = H.solve(links, m, dev(b), mode=md, naik=nk)
     say(mode, naik, info["iters"], info["reliable_updates"], info["rel_true_res"])
     assert status == H.HISQ_OK

@@ -117,3 +117,28 @@ def test_r14_roundtrip():
     Z = rng.standard_normal((10, 3, 3)) + 1j * rng.standard_normal((10, 3, 3))
     _, err = oracle.r14_pack(Z)
     assert err > 1e-3
+
+
+def test_r13_roundtrip_and_relation_to_r14():
+    """r13 keeps rows 0, 1 and one phase: exact for N = s V, V in U(3) (the
+    synthetic Naik links, s = 1/24, and a random U(3) times a random scale),
+    equal to the r14 decoding, and loudly wrong for a general matrix."""
+    L = (4, 4, 4, 6)
+    U, N = W.make_links(L, 0.3, 101)
+    P, err = oracle.r13_pack(N)
+    assert P.shape == N.shape[:-2] + (13,)
+    assert err <= 1e-14
+    back = oracle.r13_unpack(P)
+    assert np.abs(back - N).max() <= 1e-15
+    assert np.abs(back - oracle.r14_unpack(oracle.r14_pack(N)[0])).max() <= 1e-15
+    rng = np.random.default_rng(6)
+    Z = rng.standard_normal((20, 3, 3)) + 1j * rng.standard_normal((20, 3, 3))
+    Q, _ = np.linalg.qr(Z)  # a U(3) matrix per entry
+    scale = rng.uniform(0.01, 10.0, size=(20, 1, 1))
+    _, err = oracle.r13_pack(scale * Q)
+    assert err <= 1e-13
+    # the phase of c is the phase of det V (row2 = s det(V) conj(v0 x v1))
+    P, _ = oracle.r13_pack(scale * Q)
+    assert np.allclose(np.exp(1j * P[:, 12]), np.linalg.det(Q), atol=1e-13)
+    _, err = oracle.r13_pack(Z)
+    assert err > 1e-3
