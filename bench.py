@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", default="4,3,4",
                     help="Dslash tile of the solve: 'rhs_per_thread,tile_order,stage_rows' "
@@ -278,15 +279,16 @@ def main():
                 vin = vin.contiguous()
                 vout = torch.empty_like(vin)
                 packed = links.packed(prec, nk2)
-                for _ in range(3):
+                for _ in range(10):
                     H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
-                reps = 20
-                ev0.record(stream)
-                for _ in range(reps):
+                # 100 timed launches, each between its own pair of events; median
+                evs = [torch.cuda.Event(enable_timing=True) for _ in range(101)]
+                evs[0].record(stream)
+                for r in range(100):
                     H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
-                ev1.record(stream)
-                ev1.synchronize()
-                ms = ev0.elapsed_time(ev1) / reps
+                    evs[r + 1].record(stream)
+                evs[-1].synchronize()
+                ms = float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(100)]))
                 scale = 2 if prec == H.PREC_F64 else 1
                 kname = {H.NAIK_R14: "r14", H.NAIK_R13: "r13"}.get(nk2, "full")
                 byt = Vh * scale * (R.LINK_BYTES_F32[kname] + 2 * vec_b * nn)
@@ -295,22 +297,110 @@ def main():
         result["dslash_sweep"] = sweep
         log("sweep", json.dumps(sweep))
 
+        # the attainable-bandwidth reference (the paper's STREAM analogue): a
+        # 1 GiB device-to-device copy, read + write bytes over time, median of 20
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
+        evs[0].record(stream)
+        for r in range(20):
+            dst.copy_(src)
+            evs[r + 1].record(stream)
+        evs[-1].synchronize()
+        cms = float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(20)]))
+        copy_gbps = 2 * (1 << 30) / cms / 1e6
+        del src, dst
+        result["hbm_copy_GBps"] = round(copy_gbps, 1)
+        result["pct_of_copy"] = round(100 * dslash_gbps / copy_gbps, 1)
+        log("copy %.1f GB/s" % copy_gbps)
+
+    if not args.no_batched:
+        # config 4: six solves (three lattices x two masses, bundles of 3, 5, 8)
+        # in one batched launch per CG phase, against the same six solved one by one
+        probs, keep = [], []
+        j = 0
+        for Lb, nb in W.BATCHED_PROBLEMS:
+            for mb in W.BATCHED_MASSES:
+                Ub, Nb = W.make_links(Lb, 0.3, W.links_seed(4, j))
+                lb = H.Links(Lb, dev(Ub), dev(Nb), f32=False, r14=True)
+                bb = dev(W.make_sources(Lb, nb, W.sources_seed(4, j)))
+                xb = torch.empty_like(bb)
+                keep.append((Lb, nb, mb, lb, bb, xb))
+                probs.append(H.Problem(H.geom(Lb), mb, nb, lb.f64.data_ptr(),
+                                       lb.f32r14.data_ptr(), bb.data_ptr(), xb.data_ptr()))
+                j += 1
+        pb = H.hisq_default_params(mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        wsb = H.empty_bytes(H.hisq_batched_workspace_bytes(probs, H.MODE_MIXED))
+        H.hisq_cg_solve_batched(probs, pb, wsb)  # tune + warm
+        for Lb, nb, mb, lb, bb, xb in keep:
+            H.solve(lb, mb, bb, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        stb, infb = H.hisq_cg_solve_batched(probs, pb, wsb)
+        torch.cuda.synchronize()
+        t_batched = time.perf_counter() - tb
+        ts = time.perf_counter()
+        sep_iters = []
+        for Lb, nb, mb, lb, bb, xb in keep:
+            _, st1, inf1 = H.solve(lb, mb, bb, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+            sep_iters.append(inf1["total_iters"])
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - ts
+        result["batched"] = {"workload": "6 solves: %s x m in %s, mixed r14, tol 1e-10"
+                                         % (["%s n=%d" % ("x".join(map(str, Lb)), nb)
+                                             for Lb, nb in W.BATCHED_PROBLEMS], list(W.BATCHED_MASSES)),
+                             "status": stb, "batched_seconds": round(t_batched, 4),
+                             "separate_seconds": round(t_sep, 4),
+                             "speedup": round(t_sep / t_batched, 2),
+                             "iters": [i.total_iters for i in infb], "separate_iters": sep_iters}
+        log("batched", json.dumps(result["batched"]))
+        del keep, probs, wsb
+
     if not args.no_cpu_baseline:
         import oracle
+        import platform
         vh = b[:, :, :n]
-        tc = time.perf_counter()
-        reps = 0
-        while True:
-            oracle.dslash_eo(L, U, N, vh, 1)
-            reps += 1
-            if time.perf_counter() - tc > args.cpu_seconds or reps >= 10:
-                break
-        cpu_s = (time.perf_counter() - tc) / reps
+
+        def timed(fn, seconds):
+            t0c = time.perf_counter()
+            k = 0
+            while True:
+                fn()
+                k += 1
+                if time.perf_counter() - t0c > seconds or k >= 1000:
+                    return k, (time.perf_counter() - t0c) / k
+
+        # the oracle's FP64 half-Dslash on all host threads (about 2/3 of the
+        # CPU budget), its A = 4m^2 - D_eo D_oe (one CG iteration's operator)
+        reps, cpu_s = timed(lambda: oracle.dslash_eo(L, U, N, vh, 1), args.cpu_seconds * 0.6)
+        reps_a, cpu_a = timed(lambda: oracle.apply_A(L, U, N, m, vh), args.cpu_seconds * 0.25)
+        threads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        reps_1, cpu_1 = timed(lambda: oracle.dslash_eo(L, U, N, vh, 1), args.cpu_seconds * 0.15)
+        oracle.set_num_threads(threads)
         cpu_bytes = Vh * 2 * (R.LINK_BYTES_F32["full"] + 2 * vec_b * n)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        gpu_iter_s = ms_per_step / 1e3 / max(1, max(iters))
         result["cpu_baseline"] = {"value": round(cpu_bytes / cpu_s / 1e9, 3), "unit": "GB/s",
-                                  "cores": oracle.num_threads(), "kind": "oracle",
-                                  "sample": "%d FP64 half-Dslash applications, %s, %d rhs (%.1f s each)"
-                                            % (reps, "x".join(map(str, L)), n, cpu_s)}
+                                  "cores": threads, "kind": "oracle",
+                                  "sample": "%d FP64 half-Dslash applications, %s, %d rhs (%.3f s each)"
+                                            % (reps, "x".join(map(str, L)), n, cpu_s),
+                                  "cpu_model": model or platform.processor(),
+                                  "nproc": os.cpu_count(),
+                                  "one_thread_GBps": round(cpu_bytes / cpu_1 / 1e9, 3),
+                                  "cg_iteration_seconds": round(cpu_a, 4),
+                                  "cg_solve_seconds_extrapolated": round(cpu_a * max(iters), 1),
+                                  "cg_note": "A applied %d times (%.3f s each); a full solve "
+                                             "extrapolated to the GPU's %d iterations; the GPU "
+                                             "needs %.5f s per iteration" % (reps_a, cpu_a, max(iters),
+                                                                          gpu_iter_s)}
     print(json.dumps(result), flush=True)
 
     if args.copy_calibration:

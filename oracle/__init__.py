@@ -66,6 +66,7 @@ def _load():
             lib.orc_r13_pack.argtypes = [ctypes.c_long, P, P, P]
             lib.orc_r13_unpack.argtypes = [ctypes.c_long, P, P]
             lib.orc_num_threads.argtypes = []
+            lib.orc_set_threads.argtypes = [I]
             _lib = lib
     return _lib
 
@@ -96,6 +97,11 @@ def _check(rc):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    _check(_load().orc_set_threads(int(k)))
 
 
 def _links(L, U, N):

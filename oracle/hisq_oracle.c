@@ -48,6 +48,9 @@
  * -3 out of memory.  orc_cg also writes a per-rhs status: 0 converged,
  * 1 maxiter reached, 2 breakdown (Re<p,Ap> <= 0 or not finite).
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <complex.h>
 #include <math.h>
 #include <stdlib.h>
@@ -672,6 +675,17 @@ int orc_r13_unpack(long count, const double* packed, double* M)
         cross_conj(m, m + 3, w);
         for (int k = 0; k < 3; ++k) m[6 + k] = c * w[k];
     }
+    return 0;
+}
+
+/* Threads the oracle's OpenMP loops use from now on (k >= 1). */
+int orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
     return 0;
 }
 
