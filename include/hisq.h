@@ -36,6 +36,8 @@
  *            that the solvers iterate on internally.
  * Memory     every data pointer is a DEVICE pointer owned by the caller, except
  *            hisq_info / hisq_params / hisq_problem structs, which are host memory.
+ *            Field, link and workspace buffers must be 16-byte aligned (they are
+ *            read with 16-byte vector loads); HISQ_EINVAL otherwise.
  *            The library allocates no device memory; solvers take a workspace
  *            sized by hisq_workspace_bytes().  Buffers must not overlap.
  * Streams    `stream` is a hipStream_t passed as void* (NULL = default stream).

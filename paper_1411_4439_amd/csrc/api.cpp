@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <string>
@@ -62,6 +63,20 @@ int check_geom(const hisq_geom* g, Lat* lat)
     *lat = make_lat(*g);
     return HISQ_OK;
 }
+
+// Field, link and workspace buffers are read with 16-byte vector loads.
+bool misaligned(std::initializer_list<const void*> ptrs)
+{
+    for (const void* q : ptrs)
+        if (q && (reinterpret_cast<uintptr_t>(q) & 15u) != 0) return true;
+    return false;
+}
+
+#define HISQ_CHECK_ALIGNED(...)                                                     \
+    do {                                                                            \
+        if (misaligned({__VA_ARGS__}))                                              \
+            return fail(HISQ_EINVAL, "device buffers must be 16-byte aligned");     \
+    } while (0)
 
 bool valid_nr(int n, int nr)
 {
@@ -1083,6 +1098,8 @@ int check_problems(int nprob, const hisq_problem* probs, int mode)
             return fail(HISQ_EINVAL, "problem %d: nrhs = %d outside 1..8", j, probs[j].nrhs);
         if (!probs[j].links64 || !probs[j].b || !probs[j].x)
             return fail(HISQ_EINVAL, "problem %d: NULL pointer", j);
+        if (misaligned({probs[j].links64, probs[j].links32, probs[j].b, probs[j].x}))
+            return fail(HISQ_EINVAL, "problem %d: device buffers must be 16-byte aligned", j);
         if (mode == HISQ_MODE_MIXED && !probs[j].links32)
             return fail(HISQ_EINVAL, "problem %d: MIXED mode needs FP32 links", j);
         if (!std::isfinite(probs[j].mass)) return fail(HISQ_EINVAL, "problem %d: bad mass", j);
@@ -1170,6 +1187,7 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
     int rc = check_geom(g, &lat);
     if (rc) return rc;
     if (!U || !N || !packed) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(U, N, packed);
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
     if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13)
         return fail(HISQ_EINVAL, "bad naik %d", naik);
@@ -1200,6 +1218,7 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
     int rc = check_geom(g, &lat);
     if (rc) return rc;
     if (!packed || !in || !out) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(packed, in, out);
     if (out_parity != 0 && out_parity != 1) return fail(HISQ_EINVAL, "out_parity must be 0 or 1");
     if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", nrhs);
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
@@ -1245,6 +1264,7 @@ int hisq_cg_solve(const hisq_geom* g, double mass, int nrhs, const hisq_params* 
     if (rc) return rc;
     if ((rc = check_params(p, nrhs))) return rc;
     if (!links64 || !b_e || !x_e || !ws) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(links64, links32, b_e, x_e, ws);
     if (p->mode == HISQ_MODE_MIXED && !links32)
         return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
     if (!std::isfinite(mass)) return fail(HISQ_EINVAL, "mass must be finite");
@@ -1269,6 +1289,7 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     if ((rc = check_params(p, nrhs))) return rc;
     if (!links64 || !x_e || !grad_x || !grad_U || !grad_N || !grad_m || !ws)
         return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(links64, links32, x_e, grad_x, grad_U, grad_N, grad_b, ws);
     if (p->mode == HISQ_MODE_MIXED && !links32)
         return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
     Ws w;
@@ -1312,6 +1333,7 @@ int hisq_dslash_dmu(const hisq_geom* g, int out_parity, int nrhs, int nder, cons
     int rc = check_geom(g, &lat);
     if (rc) return rc;
     if (!links64 || !in || !out) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(links64, in, out);
     if (out_parity != 0 && out_parity != 1) return fail(HISQ_EINVAL, "out_parity must be 0 or 1");
     if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", nrhs);
     if (nder < 0 || nder > HISQ_MAX_DERIVATIVE)
@@ -1341,6 +1363,7 @@ static int check_full_args(const hisq_geom* g, double mass, int nrhs, const hisq
     if (rc) return rc;
     if ((rc = check_params(p, nrhs))) return rc;
     if (!links64) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(links64, links32);
     if (p->mode == HISQ_MODE_MIXED && !links32)
         return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
     if (!std::isfinite(mass) || mass == 0.0)
@@ -1358,6 +1381,7 @@ int hisq_solve_full(const hisq_geom* g, double mass, int nrhs, const hisq_params
     int rc = check_full_args(g, mass, nrhs, p, links64, links32, &lat);
     if (rc) return rc;
     if (!b_e || !b_o || !x_e || !x_o || !ws) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(b_e, b_o, x_e, x_o, ws);
     Ws w;
     const size_t need = ws_layout(lat, nrhs, p->mode, WS_FULL, nullptr, &w);
     if (ws_bytes < need)
@@ -1382,6 +1406,8 @@ int hisq_trace_estimate(const hisq_geom* g, double mass, int nrhs, const hisq_pa
     int rc = check_full_args(g, mass, nrhs, p, links64, links32, &lat);
     if (rc) return rc;
     if (!eta_e || !eta_o || !est || !ws || !orders) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(eta_e, eta_o, ws);
+    if ((reinterpret_cast<uintptr_t>(est) & 7u) != 0) return fail(HISQ_EINVAL, "est must be 8-byte aligned");
     if (ninsert < 1 || ninsert > HISQ_MAX_INSERTIONS)
         return fail(HISQ_EINVAL, "ninsert = %d outside 1..%d", ninsert, HISQ_MAX_INSERTIONS);
     for (int j = 0; j < ninsert; ++j)
@@ -1416,6 +1442,7 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
     if (rc) return rc;
     if ((rc = check_problems(nprob, probs, p->mode))) return rc;
     if (!ws) return fail(HISQ_EINVAL, "workspace is NULL");
+    HISQ_CHECK_ALIGNED(ws);
     std::vector<Ws> w;
     CgState* states;
     void* table;

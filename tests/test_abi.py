@@ -121,6 +121,13 @@ def test_errors_before_any_launch(H):
     assert rc == H.HISQ_EINVAL
     rc = lib.hisq_cg_solve_batched(0, None, ctypes.byref(p), fake, 0, None, None)
     assert rc == H.HISQ_EINVAL
+    # 16-byte alignment of every field, link and workspace buffer
+    odd = ctypes.c_void_p(0x1008)
+    rc = lib.hisq_dslash(ctypes.byref(g), 0, 1, H.PREC_F64, H.NAIK_FULL, 0, fake, odd, fake, None)
+    assert rc == H.HISQ_EINVAL and "aligned" in H.hisq_last_error()
+    rc = lib.hisq_cg_solve(ctypes.byref(g), 0.1, 1, ctypes.byref(p), fake, None, fake, fake,
+                           odd, 1 << 30, ctypes.byref(info), None)
+    assert rc == H.HISQ_EINVAL and "aligned" in H.hisq_last_error()
     # full solve and trace estimator: mass 0 cannot give x_o; bad insertion lists
     rc = lib.hisq_solve_full(ctypes.byref(g), 0.0, 1, ctypes.byref(p), fake, None, fake, fake, fake,
                              fake, fake, 1 << 30, ctypes.byref(info), None)
