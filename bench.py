@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", default="4,3,4",
                     help="Dslash tile of the solve: 'rhs_per_thread,tile_order,stage_rows' "
@@ -126,6 +127,7 @@ def main():
     Ud, Nd, bd = dev(U), dev(N), dev(b)
     links = H.Links(L, Ud, Nd, r13=not args.no_sweep)
     torch.cuda.synchronize()
+    nr = order = rows = 0
     if args.tile != "auto":
         nr, order, rows = (int(v) for v in args.tile.split(","))
         H.hisq_set_tuning(1, nr, 64, order, rows)
@@ -315,6 +317,50 @@ def main():
         result["hbm_copy_GBps"] = round(copy_gbps, 1)
         result["pct_of_copy"] = round(100 * dslash_gbps / copy_gbps, 1)
         log("copy %.1f GB/s" % copy_gbps)
+
+    if not args.no_trace:
+        # the full-matrix solve (even-odd reduction around the same CG) and one
+        # bundle of 8 Z2 noise vectors through the eq. (2) estimator term
+        # eta^dag M' M^-1 eta, at the headline shape
+        eta_e, eta_o = W.make_noise(L, n, W.sources_seed(3, 1), "z2")
+        ee, eo = dev(eta_e), dev(eta_o)
+        if args.tile != "auto":
+            H.hisq_set_tuning(1, nr, 64, order, rows)
+        wsf = H.empty_bytes(H.hisq_trace_workspace_bytes(L, n, H.MODE_MIXED))
+        H.solve_full(links, m, ee, eo, mode=H.MODE_MIXED, naik=naik, ws=wsf)  # warm
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        _, _, stf, inff = H.solve_full(links, m, ee, eo, mode=H.MODE_MIXED, naik=naik, ws=wsf)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - tf
+        tt = time.perf_counter()
+        est, stt, inft = H.trace_estimate(links, m, (1,), ee, eo, mode=H.MODE_MIXED, naik=naik, ws=wsf)
+        torch.cuda.synchronize()
+        t_trace = time.perf_counter() - tt
+        # the mu-derivative Dslash alone (FP64 links, temporal slots only):
+        # 4 links of 144 B, each input once and each output once per site
+        vo = torch.empty_like(ee)
+        for _ in range(10):
+            H.hisq_dslash_dmu(L, 1, n, 1, links.f64, ee, vo)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(51)]
+        evs[0].record(stream)
+        for r in range(50):
+            H.hisq_dslash_dmu(L, 1, n, 1, links.f64, ee, vo)
+            evs[r + 1].record(stream)
+        evs[-1].synchronize()
+        dms = float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(50)]))
+        dmu_bytes = Vh * (4 * 144 + 2 * 48 * n)
+        H.hisq_set_tuning(0)
+        result["full_and_trace"] = {
+            "full_solve_seconds": round(t_full, 4), "full_solve_status": stf,
+            "full_solve_iters": inff["iters"],
+            "trace_bundle_seconds": round(t_trace, 4), "trace_status": stt,
+            "trace_terms_per_second": round(n / t_trace, 1),
+            "trace_term_mean": [float(np.mean(est.real)), float(np.mean(est.imag))],
+            "dslash_dmu1_f64_ms": round(dms, 4),
+            "dslash_dmu1_f64_GBps": round(dmu_bytes / dms / 1e6, 1)}
+        log("full/trace", json.dumps(result["full_and_trace"]))
+        del wsf, ee, eo, vo
 
     if not args.no_batched:
         # config 4: six solves (three lattices x two masses, bundles of 3, 5, 8)
