@@ -70,7 +70,7 @@ def parse():
 # Files whose contents decide the Dslash kernels' code: a counter summary taken
 # from other contents no longer describes the kernel.
 KERNEL_SOURCES = ("paper_1411_4439_amd/csrc/dslash.hip", "paper_1411_4439_amd/csrc/stencil.h",
-                  "paper_1411_4439_amd/csrc/hisq_device.h",
+                  "paper_1411_4439_amd/csrc/naik.h", "paper_1411_4439_amd/csrc/hisq_device.h",
                   "paper_1411_4439_amd/csrc/hisq_internal.h", "paper_1411_4439_amd/build.py")
 
 
@@ -125,7 +125,7 @@ def main():
     b = W.make_sources(L, n, W.sources_seed(3))
     log("generated links and sources in %.1f s" % (time.time() - t0))
     Ud, Nd, bd = dev(U), dev(N), dev(b)
-    links = H.Links(L, Ud, Nd, r13=not args.no_sweep)
+    links = H.Links(L, Ud, Nd, r13=not args.no_sweep, r9=not args.no_sweep)
     torch.cuda.synchronize()
     nr = order = rows = 0
     if args.tile != "auto":
@@ -269,7 +269,8 @@ def main():
                  for prec, nk2, tag in ((H.PREC_F64, H.NAIK_FULL, "f64"),
                                         (H.PREC_F32, H.NAIK_FULL, "f32"),
                                         (H.PREC_F32, H.NAIK_R14, "f32_r14"),
-                                        (H.PREC_F32, H.NAIK_R13, "f32_r13"))
+                                        (H.PREC_F32, H.NAIK_R13, "f32_r13"),
+                                        (H.PREC_F32, H.NAIK_R9, "f32_r9"))
                  for nn in (1, 2, 4, 8)]
         cases.append((H.PREC_F32, H.NAIK_R14, "f32_r14_sitemajor", n, H.LAYOUT_SITE))
         for prec, nk2, tag, nn, lay in cases:
@@ -292,7 +293,7 @@ def main():
                 evs[-1].synchronize()
                 ms = float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(100)]))
                 scale = 2 if prec == H.PREC_F64 else 1
-                kname = {H.NAIK_R14: "r14", H.NAIK_R13: "r13"}.get(nk2, "full")
+                kname = {H.NAIK_R14: "r14", H.NAIK_R13: "r13", H.NAIK_R9: "r9"}.get(nk2, "full")
                 byt = Vh * scale * (R.LINK_BYTES_F32[kname] + 2 * vec_b * nn)
                 sweep["%s_n%d" % (tag, nn)] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
                                                "GFlops": round(Vh * R.FLOPS_PER_SITE_RHS * nn / ms / 1e6, 1)}

@@ -13,7 +13,7 @@
  *     periodic 4-D lattice; U, N are complex 3x3, fields complex 3-vectors.
  *   - A bundle of n rhs is n independent applications of D sharing each link
  *     load (eq. (4)).
- *   - Naik links may be stored with 14 reals ("r14", Table 1) or 13 ("r13").
+ *   - Naik links may be stored with 14 reals ("r14", Table 1), 13 or 9.
  *   - The fermion matrix is read as M = 2m + D; D is anti-Hermitian and only
  *     couples opposite parities, so the even block of M^dag M is
  *     A = 4 m^2 - D_eo D_oe, Hermitian positive definite (lambda_min >= 4 m^2).
@@ -76,11 +76,13 @@ extern "C" {
 #define HISQ_MAX_INSERTIONS 8   /* operator insertions per hisq_trace_estimate term   */
 
 enum hisq_prec { HISQ_PREC_F64 = 0, HISQ_PREC_F32 = 1 };
-/* Naik link storage (Sec. 1: reconstruction from fewer floats, Table 1 "r14"):
+/* Naik link storage (Sec. 1: reconstruction from 9 or 13/14 floats, Table 1 "r14"):
  * FULL 18 reals; R14 rows 0, 1 and one complex c with row2 = c conj(row0 x row1);
- * R13 rows 0, 1 and the phase phi of c, |c| = 1 / |row0|.  R14 and R13 are exact
- * for N = s V with V in U(3), s > 0, and FP32 only. */
-enum hisq_naik { HISQ_NAIK_FULL = 0, HISQ_NAIK_R14 = 1, HISQ_NAIK_R13 = 2 };
+ * R13 rows 0, 1 and the phase phi of c, |c| = 1 / |row0|; R9 one Hermitian H
+ * with N = s exp(iH), s one scale for the whole field.  R14, R13 and R9 are
+ * exact for N = s V with V in U(3), s > 0 (R9: the same s everywhere), and FP32
+ * only. */
+enum hisq_naik { HISQ_NAIK_FULL = 0, HISQ_NAIK_R14 = 1, HISQ_NAIK_R13 = 2, HISQ_NAIK_R9 = 3 };
 enum hisq_mode { HISQ_MODE_FP64 = 0, HISQ_MODE_MIXED = 1 };
 /* field order: [Vh][3][n] (site-major, the default) or [3][Vh][n] */
 enum hisq_layout { HISQ_LAYOUT_SITE = 0, HISQ_LAYOUT_COLOUR = 1 };
@@ -145,7 +147,7 @@ void hisq_default_params(hisq_params* p);
 
 /*
  * Size in bytes of a packed link buffer for `prec` (HISQ_PREC_*) and Naik
- * storage `naik` (HISQ_NAIK_*; R14 and R13 only with F32).  0 on invalid input.
+ * storage `naik` (HISQ_NAIK_*; R14, R13 and R9 only with F32).  0 on invalid input.
  */
 size_t hisq_links_bytes(const hisq_geom* g, int prec, int naik);
 
@@ -171,10 +173,12 @@ size_t hisq_trace_workspace_bytes(const hisq_geom* g, int nrhs, int mode);
  * (device, hisq_links_bytes(g, prec, naik) bytes) for the Dslash of eq. (3).
  * For naik = R14 every Naik link (and its adjoint) is stored as rows 0, 1 and
  * one complex c with row2 = c conj(row0 x row1); for R13 as rows 0, 1 and the
- * phase of c, whose modulus 1/|row0| follows from N = s V, V in U(3).  Both
- * then synchronize `stream` and return HISQ_EPACK if any round-trip error
- * exceeds 1e-6 of the link's norm (N is not a positive multiple of a U(3)
- * matrix).
+ * phase of c, whose modulus 1/|row0| follows from N = s V, V in U(3); for R9
+ * as the 9 reals of H = -i log(N / s) with s = |det N|^(1/3).  These calls then
+ * synchronize `stream` and return HISQ_EPACK if any round-trip error exceeds
+ * 1e-6 of the link's norm (4e-6 for R9, whose FP32 H rounds at that level), or,
+ * for R9, if the scales s of the Naik links differ by more than 1e-6 (N is not
+ * a positive multiple of a U(3) matrix, or not one multiple throughout).
  */
 int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int prec, int naik,
                     void* packed, void* stream);

@@ -229,6 +229,45 @@ def r13_unpack(P):
     return M
 
 
+def r9_pack(M):
+    """r9: N = s exp(iH) with one scale s for all matrices, s = |det N|^(1/3)
+    (their mean), H = -i log(N / s) Hermitian (9 reals: H00, H11, H22, Re/Im
+    H01, H02, H12).  Returns (packed (..., 9), s, max relative round-trip error,
+    relative spread of the per-matrix scales).  Uses scipy's matrix log/exp."""
+    from scipy.linalg import expm, logm
+    M = _c128(M)
+    lead = M.shape[:-2]
+    flat = M.reshape(-1, 3, 3)
+    sj = np.abs(np.linalg.det(flat)) ** (1.0 / 3.0)
+    s = float(sj.mean())
+    out = np.empty((flat.shape[0], 9))
+    worst = 0.0
+    for j, m in enumerate(flat):
+        H = -1j * logm(m / sj[j])
+        H = 0.5 * (H + H.conj().T)
+        out[j] = [H[0, 0].real, H[1, 1].real, H[2, 2].real, H[0, 1].real, H[0, 1].imag,
+                  H[0, 2].real, H[0, 2].imag, H[1, 2].real, H[1, 2].imag]
+        back = sj[j] * expm(1j * H)
+        worst = max(worst, np.linalg.norm(back - m) / np.linalg.norm(m))
+    spread = float((sj.max() - sj.min()) / sj.max()) if sj.size else 0.0
+    return out.reshape(lead + (9,)), s, worst, spread
+
+
+def r9_unpack(P, s):
+    """s exp(iH) from the 9 reals of H."""
+    from scipy.linalg import expm
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    lead = P.shape[:-1]
+    flat = P.reshape(-1, 9)
+    out = np.empty((flat.shape[0], 3, 3), dtype=np.complex128)
+    for j, h in enumerate(flat):
+        H = np.array([[h[0], h[3] + 1j * h[4], h[5] + 1j * h[6]],
+                      [h[3] - 1j * h[4], h[1], h[7] + 1j * h[8]],
+                      [h[5] - 1j * h[6], h[7] - 1j * h[8], h[2]]])
+        out[j] = s * expm(1j * H)
+    return out.reshape(lead + (3, 3))
+
+
 def dslash_dmu(L, U, N, v, out_parity, nder, mu=0.0):
     """d^n D(mu) / d mu^n restricted to one output parity (input parity
     1 - out_parity); nder = 0 is D(mu).  Temporal h-hops carry exp(h mu)."""

@@ -78,6 +78,17 @@ bool misaligned(std::initializer_list<const void*> ptrs)
             return fail(HISQ_EINVAL, "device buffers must be 16-byte aligned");     \
     } while (0)
 
+bool valid_naik(int nk)
+{
+    return nk == HISQ_NAIK_FULL || nk == HISQ_NAIK_R14 || nk == HISQ_NAIK_R13 || nk == HISQ_NAIK_R9;
+}
+
+// r9 links: the Naik scale the kernels read, in the buffer's header
+const float* naik_scale_of(const void* packed)
+{
+    return packed ? &reinterpret_cast<const LinkHeader*>(packed)->naik_scale : nullptr;
+}
+
 bool valid_nr(int n, int nr)
 {
     if (nr < 1 || nr > n || n % nr != 0) return false;
@@ -187,14 +198,32 @@ hipError_t launch_ds(int epi, int n, int nk, const Tile& t, const DslashArgs<flo
     return launch_dslash_f32(epi, nk, n, t, a, s, cm);
 }
 
+bool t_order_ok(const Lat& lat, int G, int bs, int order);
+
+// The tile of a kernel without LDS staging (the p-update, the batched
+// kernels): a staged Dslash tile may hold up to kMaxBlockLds threads, more
+// than those kernels are built for, so it falls back to 128 threads.
+Tile unstaged(const Tile& t, const Lat& lat)
+{
+    if (t.rows == 0 && t.bs <= kMaxBlock) return t;
+    (void)lat;
+    return Tile{t.nr, 128, t.remap, 0};
+}
+
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStream_t s)
 {
-    return pupdate_flat_ok(n) ? launch_pupdate_flat_f64(n, a, s) : launch_pupdate_f64(n, t, a, s);
+    if (pupdate_flat_ok(n)) return launch_pupdate_flat_f64(n, a, s);
+    Tile u = unstaged(t, a.lat);
+    if (!t_order_ok(a.lat, n / u.nr, u.bs, u.remap)) u.remap = 1;
+    return launch_pupdate_f64(n, u, a, s);
 }
 
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<float>& a, hipStream_t s)
 {
-    return pupdate_flat_ok(n) ? launch_pupdate_flat_f32(n, a, s) : launch_pupdate_f32(n, t, a, s);
+    if (pupdate_flat_ok(n)) return launch_pupdate_flat_f32(n, a, s);
+    Tile u = unstaged(t, a.lat);
+    if (!t_order_ok(a.lat, n / u.nr, u.bs, u.remap)) u.remap = 1;
+    return launch_pupdate_f32(n, u, a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -478,6 +507,7 @@ struct Engine {
         k2.lat = q.lat;
         k2.parity = 1;
         k2.links = link_block<T>(L, q.lat.Vh, rr, 1);
+        k2.naik_scale = naik_scale_of(L);
         k2.in = p;
         k2.out = t;
         k2.mass4 = q.m4;
@@ -858,6 +888,7 @@ int Engine::run(hisq_info* infos)
             p32.lat = q.lat;
             p32.parity = 1;
             p32.links = link_block<float>(q.links32, q.lat.Vh, nk, 1);
+            p32.naik_scale = naik_scale_of(q.links32);
             p32.in = q.w.p32;
             p32.out = q.w.t32;
             p32.mass4 = q.m4;
@@ -873,7 +904,7 @@ int Engine::run(hisq_info* infos)
         size_t big = 0;
         for (size_t j = 1; j < P.size(); ++j)
             if (P[j].lat.Vh * P[j].n > P[big].lat.Vh * P[big].n) big = j;
-        batch_bs = mixed ? P[big].t32.bs : P[big].t64.bs;
+        batch_bs = unstaged(mixed ? P[big].t32 : P[big].t64, P[big].lat).bs;
         static thread_local std::vector<char> tabbuf;
         tabbuf.resize(std::max(sizeof(BatchTable<double>), sizeof(BatchTable<float>)));
         rc = mixed ? upload_table<float>(tabbuf.data()) : upload_table<double>(tabbuf.data());
@@ -932,7 +963,7 @@ int check_params(const hisq_params* p, int n)
     if (n < 1 || n > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", n);
     if (p->mode != HISQ_MODE_FP64 && p->mode != HISQ_MODE_MIXED)
         return fail(HISQ_EINVAL, "unknown mode %d", p->mode);
-    if (p->naik != HISQ_NAIK_FULL && p->naik != HISQ_NAIK_R14 && p->naik != HISQ_NAIK_R13)
+    if (!valid_naik(p->naik))
         return fail(HISQ_EINVAL, "unknown naik storage %d", p->naik);
     if (!(p->tol > 0) || !std::isfinite(p->tol)) return fail(HISQ_EINVAL, "tol must be > 0");
     if (p->maxiter < 0) return fail(HISQ_EINVAL, "maxiter must be >= 0");
@@ -1133,7 +1164,7 @@ size_t hisq_links_bytes(const hisq_geom* g, int prec, int naik)
     Lat lat;
     if (check_geom(g, &lat)) return 0;
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return 0;
-    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13) return 0;
+    if (!valid_naik(naik)) return 0;
     if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32) return 0;
     const size_t elem = prec == HISQ_PREC_F64 ? sizeof(d2) : sizeof(f2);
     return kLinkHeaderBytes + 2 * link_block_reals(lat.Vh, naik) * (elem / 2);
@@ -1189,23 +1220,33 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
     if (!U || !N || !packed) return fail(HISQ_EINVAL, "NULL pointer");
     HISQ_CHECK_ALIGNED(U, N, packed);
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
-    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13)
+    if (!valid_naik(naik))
         return fail(HISQ_EINVAL, "bad naik %d", naik);
     if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32)
-        return fail(HISQ_EINVAL, "r14 / r13 Naik storage is FP32 only");
+        return fail(HISQ_EINVAL, "compressed Naik storage is FP32 only");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(launch_pack(lat, reinterpret_cast<const d2*>(U), reinterpret_cast<const d2*>(N), prec,
                         naik, packed, s));
     if (naik != HISQ_NAIK_FULL) {
-        uint32_t bits = 0;
-        const LinkHeader* h = reinterpret_cast<const LinkHeader*>(packed);
-        HIP_TRY(hipMemcpyAsync(&bits, &h->naik_err_bits, sizeof(bits), hipMemcpyDeviceToHost, s));
+        LinkHeader h{};
+        HIP_TRY(hipMemcpyAsync(&h, packed, sizeof(h), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        float err;
-        std::memcpy(&err, &bits, sizeof(err));
-        if (!(err <= kNaikTolerance))
-            return fail(HISQ_EPACK, "%s round-trip error %g: Naik links are not s * U(3)",
-                        naik == HISQ_NAIK_R14 ? "r14" : "r13", err);
+        float err, smin, smax;
+        std::memcpy(&err, &h.naik_err_bits, sizeof(err));
+        std::memcpy(&smin, &h.scale_min_bits, sizeof(smin));
+        std::memcpy(&smax, &h.scale_max_bits, sizeof(smax));
+        const char* name = naik == HISQ_NAIK_R14 ? "r14" : naik == HISQ_NAIK_R13 ? "r13" : "r9";
+        const float tol = naik == HISQ_NAIK_R9 ? kR9Tolerance : kNaikTolerance;
+        if (!(err <= tol))
+            return fail(HISQ_EPACK, "%s round-trip error %g: Naik links are not s * U(3)", name, err);
+        if (naik == HISQ_NAIK_R9) {
+            if (!(smin > 0.0f) || !(smax - smin <= kR9ScaleSpread * smax))
+                return fail(HISQ_EPACK, "r9 needs one Naik scale: |det N|^(1/3) spans %g .. %g", smin, smax);
+            const float scale = 0.5f * (smin + smax);
+            LinkHeader* hd = reinterpret_cast<LinkHeader*>(packed);
+            HIP_TRY(hipMemcpyAsync(&hd->naik_scale, &scale, sizeof(scale), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
     }
     return HISQ_OK;
 }
@@ -1222,10 +1263,10 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
     if (out_parity != 0 && out_parity != 1) return fail(HISQ_EINVAL, "out_parity must be 0 or 1");
     if (nrhs < 1 || nrhs > HISQ_MAX_RHS) return fail(HISQ_EINVAL, "nrhs = %d outside 1..8", nrhs);
     if (prec != HISQ_PREC_F64 && prec != HISQ_PREC_F32) return fail(HISQ_EINVAL, "bad prec %d", prec);
-    if (naik != HISQ_NAIK_FULL && naik != HISQ_NAIK_R14 && naik != HISQ_NAIK_R13)
+    if (!valid_naik(naik))
         return fail(HISQ_EINVAL, "bad naik %d", naik);
     if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32)
-        return fail(HISQ_EINVAL, "r14 / r13 Naik storage is FP32 only");
+        return fail(HISQ_EINVAL, "compressed Naik storage is FP32 only");
     if (layout != HISQ_LAYOUT_SITE && layout != HISQ_LAYOUT_COLOUR)
         return fail(HISQ_EINVAL, "bad layout %d", layout);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1246,6 +1287,7 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
         a.lat = lat;
         a.parity = out_parity;
         a.links = link_block<float>(packed, lat.Vh, nk, out_parity);
+        a.naik_scale = naik_scale_of(packed);
         a.in = reinterpret_cast<const f2*>(in);
         a.out = reinterpret_cast<f2*>(out);
         if ((rc = get_tile(lat, nrhs, prec, nk, a, s, &t, EPI_PLAIN, cm))) return rc;

@@ -178,6 +178,7 @@ hipError_t launch_pupdate_flat_f32(int nrhs, const PupdateArgs<float>& a, hipStr
 hipError_t launch_pupdate_batched_f64(const BatchTable<double>* tab, int total_blocks, int bs,
                                       hipStream_t s)
 {
+    if (bs < 64 || bs > kMaxBlock || bs % 64 != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pupdate_batched<double>, dim3(total_blocks), dim3(bs), 0, s, tab);
     return hipGetLastError();
 }
@@ -185,6 +186,7 @@ hipError_t launch_pupdate_batched_f64(const BatchTable<double>* tab, int total_b
 hipError_t launch_pupdate_batched_f32(const BatchTable<float>* tab, int total_blocks, int bs,
                                       hipStream_t s)
 {
+    if (bs < 64 || bs > kMaxBlock || bs % 64 != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_pupdate_batched<float>, dim3(total_blocks), dim3(bs), 0, s, tab);
     return hipGetLastError();
 }
@@ -193,6 +195,7 @@ template <typename T, int NRHS, int NR>
 static hipError_t go_pup(const Tile& t, PupdateArgs<T> a, hipStream_t s)
 {
     constexpr int G = NRHS / NR;
+    if (t.bs < 64 || t.bs > kMaxBlock || t.bs % 64 != 0) return hipErrorInvalidValue;
     const long threads = (long)a.lat.Vh * G;
     a.ntiles = (int)((threads + t.bs - 1) / t.bs);
     a.remap = t.remap;

@@ -11,10 +11,11 @@
 //
 // This file is compiled once per (precision, Naik storage, epilogue):
 //   HISQ_KPREC 0 = FP64, 1 = FP32, 2 = FP32 with r14 Naik links,
-//              3 = FP32 with r13 Naik links
+//              3 = FP32 with r13 Naik links, 4 = FP32 with r9 Naik links
 //   HISQ_KEPI  one of EPI_PLAIN, EPI_NORM, EPI_CG, EPI_RESID
 #include <type_traits>
 
+#include "naik.h"
 #include "stencil.h"
 
 #ifndef HISQ_KPREC
@@ -35,9 +36,12 @@ constexpr int kNK = HISQ_NAIK_FULL;
 #elif HISQ_KPREC == 2
 using KT = float;
 constexpr int kNK = HISQ_NAIK_R14;
-#else
+#elif HISQ_KPREC == 3
 using KT = float;
 constexpr int kNK = HISQ_NAIK_R13;
+#else
+using KT = float;
+constexpr int kNK = HISQ_NAIK_R9;
 #endif
 
 template <typename T, int NRHS, int NR, bool CM>
@@ -48,31 +52,6 @@ __device__ __forceinline__ void load_vec(const cplx<T>* __restrict__ in, int Vh,
     const cplx<T>* vp = in + Lay::site(nbr) + g * NR;
 #pragma unroll
     for (int b = 0; b < 3; ++b) load_rhs<NR>(vp + Lay::colour(b, Vh), v[b]);
-}
-
-// exp(i phi) for phi in [-pi, pi] (the packer stores atan2's result): Taylor
-// series of sin and cos at phi/2 in [-pi/2, pi/2] (truncation below 6e-8),
-// then the double-angle formulas; within 4e-7 of the exact value in FP32.
-// A library sincosf inlines a large-argument reduction that costs this kernel
-// its registers.
-__device__ __forceinline__ void unit_phase(float phi, float* cs, float* sn)
-{
-    const float t = 0.5f * phi, t2 = t * t;
-    float s = 1.0f - t2 * (1.0f / (12 * 13));
-    s = 1.0f - t2 * (1.0f / (10 * 11)) * s;
-    s = 1.0f - t2 * (1.0f / (8 * 9)) * s;
-    s = 1.0f - t2 * (1.0f / (6 * 7)) * s;
-    s = 1.0f - t2 * (1.0f / (4 * 5)) * s;
-    s = t * (1.0f - t2 * (1.0f / (2 * 3)) * s);
-    float c = 1.0f - t2 * (1.0f / (13 * 14));
-    c = 1.0f - t2 * (1.0f / (11 * 12)) * c;
-    c = 1.0f - t2 * (1.0f / (9 * 10)) * c;
-    c = 1.0f - t2 * (1.0f / (7 * 8)) * c;
-    c = 1.0f - t2 * (1.0f / (5 * 6)) * c;
-    c = 1.0f - t2 * (1.0f / (3 * 4)) * c;
-    c = 1.0f - t2 * (1.0f / (1 * 2)) * c;
-    *cs = c * c - s * s;
-    *sn = 2.0f * s * c;
 }
 
 // Naik storage r13: c = exp(i phi) / |row0|, phi loaded into m[6].x (for
@@ -89,11 +68,26 @@ __device__ __forceinline__ cplx<T> r13_coefficient(const cplx<T> (&m)[9])
     return cplx<T>{cs * inv, sn * inv};
 }
 
+// Naik storage r9: m[0..3] and m[4].x hold the 9 reals of H; the matrix is
+// ns exp(iH), ns the field's Naik scale.
+template <typename T>
+__device__ __forceinline__ void r9_matrix(cplx<T> (&m)[9], T ns)
+{
+    static_assert(sizeof(T) == 4, "r9 is an FP32 storage");
+    const T h[9] = {m[0].x, m[0].y, m[1].x, m[1].y, m[2].x, m[2].y, m[3].x, m[3].y, m[4].x};
+    T re[9], im[9];
+    expi_hermitian<T>(h, ns, re, im);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[e] = cplx<T>{re[e], im[e]};
+}
+
 template <typename T, int NR, int NK, int S>
 __device__ __forceinline__ void apply_slot(cplx<T> (&m)[9], const cplx<T> (&v)[3][NR],
-                                           cplx<T> (&acc)[3][NR])
+                                           cplx<T> (&acc)[3][NR], T ns)
 {
-    if constexpr (NK != HISQ_NAIK_FULL && S >= 8) {
+    if constexpr (NK == HISQ_NAIK_R9 && S >= 8) {
+        r9_matrix<T>(m, ns);
+    } else if constexpr (NK != HISQ_NAIK_FULL && S >= 8) {
         // row 2 = c * conj(row0 x row1); r14 loaded c into m[6], r13 its phase
         cplx<T> cc = m[6];
         if constexpr (NK == HISQ_NAIK_R13) cc = r13_coefficient<T>(m);
@@ -131,7 +125,7 @@ template <typename T, int NRHS, int NR, int NK, bool CM>
 __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
                                             const cplx<T>* __restrict__ lk,
                                             const cplx<T>* __restrict__ in,
-                                            cplx<T> (&acc)[3][NR])
+                                            cplx<T> (&acc)[3][NR], T ns)
 {
     using C = cplx<T>;
     const int Vh = lat.Vh;
@@ -159,7 +153,7 @@ __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
         if constexpr (k + 1 < 16)
             load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(k + 1)>(lat, sc), g, v[(k + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
-        apply_slot<T, NR, NK, slot_at(k)>(m[k % (LD + 1)], v[k & 1], acc);
+        apply_slot<T, NR, NK, slot_at(k)>(m[k % (LD + 1)], v[k & 1], acc, ns);
         __builtin_amdgcn_sched_barrier(0);
     });
 }
@@ -245,7 +239,7 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
                                                 const cplx<T>* __restrict__ lk,
                                                 const cplx<T>* __restrict__ in,
                                                 const cplx<T>* lds, int rows,
-                                                cplx<T> (&acc)[3][NR])
+                                                cplx<T> (&acc)[3][NR], T ns)
 {
     using C = cplx<T>;
     const int Vh = lat.Vh;
@@ -267,7 +261,7 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
         if constexpr (k % 2 == 0) {
             load_link<T, NK, slot_at(k + 1)>(lk, Vh, i, m[(k + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
-            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vg[(k >> 1) & 1], acc);
+            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vg[(k >> 1) & 1], acc, ns);
             __builtin_amdgcn_sched_barrier(0);
             if constexpr (k + 2 < 16) load_link<T, NK, slot_at(k + 2)>(lk, Vh, i, m[k & 1]);
             if constexpr (k + 4 < 16)
@@ -276,7 +270,7 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
             load_vec_lds<T, NRHS, NR>(lds, cstride,
                                       lds_neighbour<slot_at(k + 1)>(lat, r, xh, sc.x), g, vl);
         } else {
-            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vl, acc);
+            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vl, acc, ns);
         }
         __builtin_amdgcn_sched_barrier(0);
     });
@@ -373,6 +367,8 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
         any_act = any_act || act[k];
     }
     const T m4 = (T)a.mass4;
+    T ns = T(1);  // r9: the Naik scale of the links
+    if constexpr (NK == HISQ_NAIK_R9) ns = (T)*a.naik_scale;
 
     const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
     if constexpr (ST) {
@@ -386,9 +382,9 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
         if constexpr (ST)
             dslash_site_lds<T, NRHS, NR, NK>(a.lat, a.parity, i, g,
                                               ((int)threadIdx.x / G) / a.lat.Lh0, a.links, a.in,
-                                              lds, a.rows + 6, acc);
+                                              lds, a.rows + 6, acc, ns);
         else
-            dslash_site<T, NRHS, NR, NK, CM>(a.lat, a.parity, i, g, a.links, a.in, acc);
+            dslash_site<T, NRHS, NR, NK, CM>(a.lat, a.parity, i, g, a.links, a.in, acc, ns);
         pin_acc(acc);
         using Lay = Layout<NRHS, CM>;
         const int base = Lay::site(i) + g * NR;
@@ -514,6 +510,10 @@ static hipError_t go(const Tile& t, DslashArgs<T> a, hipStream_t s, bool cm)
     a.ntiles = (int)((threads + t.bs - 1) / t.bs);
     a.remap = t.remap;
     a.rows = t.rows;
+    // each kernel is built for a maximum work-group size; the grid
+    // reductions need whole waves
+    if (t.bs < 64 || t.bs % 64 != 0 || t.bs > (t.rows > 0 ? kMaxBlockLds : kMaxBlock))
+        return hipErrorInvalidValue;
     if (t.rows > 0) {
         // LDS-staged: colour-major only; the host has checked that a tile is
         // t.rows whole x-rows of one plane and that the rows fit in LDS
@@ -573,6 +573,8 @@ hipError_t HISQ_LAUNCH_NAME(int nrhs, const Tile& t, const DslashArgs<KT>& a, hi
 #define HISQ_BNAME HISQ_CAT(HISQ_CAT(HISQ_CAT(launch_dslash_batched_p, HISQ_KPREC), _e), HISQ_KEPI)
 hipError_t HISQ_BNAME(const BatchTable<KT>* tab, int total_blocks, int bs, hipStream_t s)
 {
+    // built for at most kMaxBlock threads, whole waves (the grid reductions)
+    if (bs < 64 || bs > kMaxBlock || bs % 64 != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_dslash_batched<KT, kNK, HISQ_KEPI>), dim3(total_blocks), dim3(bs), 0, s,
                        tab);
     return hipGetLastError();

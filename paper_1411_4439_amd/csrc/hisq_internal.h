@@ -56,13 +56,18 @@ constexpr int kMaxBlock = 256;
 constexpr int kMaxBlockLds = 512;
 constexpr int kMaxStageBytes = 64 * 1024;
 constexpr float kNaikTolerance = 1e-6f;  // r14 / r13 round-trip error bound
+constexpr float kR9Tolerance = 4e-6f;    // r9: bounded by the FP32 rounding of H
+constexpr float kR9ScaleSpread = 1e-6f;  // r9: relative spread of the Naik scales
 
 struct LinkHeader {
     uint32_t magic;
     int32_t L[4];
     int32_t prec;
     int32_t naik;
-    uint32_t naik_err_bits;  // r14 / r13: max relative round-trip error, float bits (atomicMax)
+    uint32_t naik_err_bits;  // r14 / r13 / r9: max relative round-trip error, float bits (atomicMax)
+    uint32_t scale_min_bits;  // r9: smallest and largest Naik scale |det N|^(1/3), float bits
+    uint32_t scale_max_bits;
+    float naik_scale;         // r9: the scale the kernels apply (set after packing)
 };
 
 // Lattice description as the kernels see it.
@@ -89,10 +94,11 @@ inline Lat make_lat(const hisq_geom& g)
 // -N^dag bwd per direction), each one matrix per site.  Sizes in reals (float or
 // double).  U slots hold 18 reals; a Naik slot holds 18 (FULL), 14 (R14: rows 0
 // and 1 and one complex c with row2 = c conj(row0 x row1)) or 13 (R13: rows 0
-// and 1 and the phase phi of c = exp(i phi) / |row0|).  R14 and R13 are FP32.
+// and 1 and the phase phi of c = exp(i phi) / |row0|) or 9 (R9: Hermitian H,
+// N = s exp(iH) with s in the header).  R14, R13 and R9 are FP32.
 __host__ __device__ constexpr int naik_reals(int nk)
 {
-    return nk == HISQ_NAIK_R14 ? 14 : nk == HISQ_NAIK_R13 ? 13 : 18;
+    return nk == HISQ_NAIK_R14 ? 14 : nk == HISQ_NAIK_R13 ? 13 : nk == HISQ_NAIK_R9 ? 9 : 18;
 }
 
 __host__ __device__ constexpr int slot_reals(int slot, int nk) { return slot < 8 ? 18 : naik_reals(nk); }
@@ -167,6 +173,7 @@ struct DslashArgs {
     int ntiles;
     int remap;
     int rows;  // LDS-staged x-rows per tile (0: unstaged)
+    const float* naik_scale;  // r9 links: the scale in their header
 };
 
 template <typename T>

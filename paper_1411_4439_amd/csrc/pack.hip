@@ -7,8 +7,11 @@
 // w = conj(row0 x row1), so that row2 = c w exactly when the matrix is a
 // positive multiple of a U(3) matrix; the worst relative round-trip error is
 // kept in the buffer header (atomicMax on the float's bits, valid for
-// non-negative floats).
+// non-negative floats).  In r9 storage a Naik slot keeps H = -i log(M / s),
+// s = |det M|^(1/3); the header tracks the smallest and largest s, and the
+// round trip is checked through the FP32 decoder on the FP32-rounded H.
 #include "hisq_device.h"
+#include "naik.h"
 
 namespace hisq {
 
@@ -72,7 +75,42 @@ __global__ void k_pack(Lat lat, const d2* __restrict__ U, const d2* __restrict__
         }
         T* dst = blk + (size_t)slot_real_start(slot, NK) * Vh;
         const int nr = slot_reals(slot, NK);
-        if (NK != HISQ_NAIK_FULL && slot >= 8) {
+        if (NK == HISQ_NAIK_R9 && slot >= 8) {
+            // s = |det M|^(1/3), W = M / s, H = -i log W
+            Cx<double> Wm[9];
+            for (int e = 0; e < 9; ++e) Wm[e] = Cx<double>{m[e].x, m[e].y};
+            const Cx<double> a1 = cx_mul(Wm[4], Wm[8]), a2 = cx_mul(Wm[5], Wm[7]);
+            const Cx<double> b1 = cx_mul(Wm[3], Wm[8]), b2 = cx_mul(Wm[5], Wm[6]);
+            const Cx<double> g1 = cx_mul(Wm[3], Wm[7]), g2 = cx_mul(Wm[4], Wm[6]);
+            const Cx<double> t0 = cx_mul(Wm[0], Cx<double>{a1.re - a2.re, a1.im - a2.im});
+            const Cx<double> t1 = cx_mul(Wm[1], Cx<double>{b1.re - b2.re, b1.im - b2.im});
+            const Cx<double> t2 = cx_mul(Wm[2], Cx<double>{g1.re - g2.re, g1.im - g2.im});
+            const double dre = t0.re - t1.re + t2.re, dim = t0.im - t1.im + t2.im;
+            const double sc = cbrt(sqrt(dre * dre + dim * dim));
+            double hreal[9];
+            double fro = 0, err = 0;
+            for (int e = 0; e < 9; ++e) fro += m[e].x * m[e].x + m[e].y * m[e].y;
+            if (sc > 0) {
+                for (int e = 0; e < 9; ++e) Wm[e] = Cx<double>{m[e].x / sc, m[e].y / sc};
+                log_unitary(Wm, hreal);
+                float hf[9], ore[9], oim[9];
+                for (int e = 0; e < 9; ++e) hf[e] = (float)hreal[e];
+                expi_hermitian<float>(hf, (float)sc, ore, oim);
+                for (int e = 0; e < 9; ++e) {
+                    const double dx = ore[e] - m[e].x, dy = oim[e] - m[e].y;
+                    err += dx * dx + dy * dy;
+                }
+            } else {
+                for (int e = 0; e < 9; ++e) hreal[e] = 0;
+                err = fro;
+            }
+            const double rel = fro > 0 ? sqrt(err / fro) : 0.0;
+            worst = fmaxf(worst, (rel == rel) ? (float)rel : 3.0e38f);
+            const float scf = (float)sc;
+            atomicMin(&hdr->scale_min_bits, __float_as_uint(scf));
+            atomicMax(&hdr->scale_max_bits, __float_as_uint(scf));
+            for (int e = 0; e < 9; ++e) put(dst, nr, e, (T)hreal[e]);
+        } else if (NK != HISQ_NAIK_FULL && slot >= 8) {
             // w = conj(row0 x row1); c = <w, row2> / |w|^2
             d2 w[3];
             w[0] = cmul_d(m[1], m[5]) - cmul_d(m[2], m[4]);
@@ -132,6 +170,9 @@ hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int n
     h.prec = prec;
     h.naik = naik;
     h.naik_err_bits = 0u;
+    h.scale_min_bits = 0x7f800000u;  // +inf
+    h.scale_max_bits = 0u;
+    h.naik_scale = 1.0f;
     LinkHeader* hdr = reinterpret_cast<LinkHeader*>(packed);
     hipLaunchKernelGGL(k_pack_header, dim3(1), dim3(1), 0, s, h, hdr);
     hipError_t e = hipGetLastError();
@@ -146,6 +187,9 @@ hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int n
                            reinterpret_cast<float*>(body), hdr);
     else if (naik == HISQ_NAIK_R13)
         hipLaunchKernelGGL((k_pack<float, HISQ_NAIK_R13>), dim3(grid), dim3(bs), 0, s, lat, U, N,
+                           reinterpret_cast<float*>(body), hdr);
+    else if (naik == HISQ_NAIK_R9)
+        hipLaunchKernelGGL((k_pack<float, HISQ_NAIK_R9>), dim3(grid), dim3(bs), 0, s, lat, U, N,
                            reinterpret_cast<float*>(body), hdr);
     else
         hipLaunchKernelGGL((k_pack<float, HISQ_NAIK_FULL>), dim3(grid), dim3(bs), 0, s, lat, U, N,

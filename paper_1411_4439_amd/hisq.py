@@ -27,7 +27,7 @@ HISQ_EINVAL, HISQ_EGEOM, HISQ_EWORKSPACE, HISQ_EPACK, HISQ_EHIP = -1, -2, -3, -4
 HISQ_NOT_CONVERGED, HISQ_BREAKDOWN = 1, 2
 HISQ_MAX_RHS, HISQ_MAX_PROBLEMS = 8, 16
 PREC_F64, PREC_F32 = 0, 1
-NAIK_FULL, NAIK_R14, NAIK_R13 = 0, 1, 2
+NAIK_FULL, NAIK_R14, NAIK_R13, NAIK_R9 = 0, 1, 2, 3
 MODE_FP64, MODE_MIXED = 0, 1
 LAYOUT_SITE, LAYOUT_COLOUR = 0, 1
 K_PUPDATE, K_DSLASH_OE, K_DSLASH_EO, K_RELIABLE = 0, 1, 2, 3
@@ -248,9 +248,10 @@ def empty_bytes(nbytes, device="cuda"):
 
 class Links:
     """Packed link buffers for one gauge field: FP64 full, and optionally FP32
-    full, FP32 r14 and FP32 r13.  U, N: [4][V][3][3] complex128 device tensors."""
+    full, FP32 r14, FP32 r13 and FP32 r9.  U, N: [4][V][3][3] complex128 device
+    tensors."""
 
-    def __init__(self, L, U, N, f32=True, r14=True, r13=False, stream=None):
+    def __init__(self, L, U, N, f32=True, r14=True, r13=False, r9=False, stream=None):
         self.L = tuple(int(v) for v in L)
         U = U.contiguous()
         N = N.contiguous()
@@ -259,6 +260,7 @@ class Links:
         self.f32 = None
         self.f32r14 = None
         self.f32r13 = None
+        self.f32r9 = None
         if f32:
             self.f32 = empty_bytes(hisq_links_bytes(self.L, PREC_F32, NAIK_FULL), U.device)
             hisq_pack_links(self.L, U, N, PREC_F32, NAIK_FULL, self.f32, stream)
@@ -268,11 +270,14 @@ class Links:
         if r13:
             self.f32r13 = empty_bytes(hisq_links_bytes(self.L, PREC_F32, NAIK_R13), U.device)
             hisq_pack_links(self.L, U, N, PREC_F32, NAIK_R13, self.f32r13, stream)
+        if r9:
+            self.f32r9 = empty_bytes(hisq_links_bytes(self.L, PREC_F32, NAIK_R9), U.device)
+            hisq_pack_links(self.L, U, N, PREC_F32, NAIK_R9, self.f32r9, stream)
 
     def packed(self, prec, naik=NAIK_FULL):
         if prec == PREC_F64:
             return self.f64
-        return {NAIK_R14: self.f32r14, NAIK_R13: self.f32r13}.get(naik, self.f32)
+        return {NAIK_R14: self.f32r14, NAIK_R13: self.f32r13, NAIK_R9: self.f32r9}.get(naik, self.f32)
 
 
 def dslash(links, out_parity, v, prec=PREC_F64, naik=NAIK_FULL, stream=None, layout=LAYOUT_SITE):

@@ -19,7 +19,8 @@ minimum: links once, every input vector once, every output vector once, i.e.
 from __future__ import annotations
 
 FLOPS_PER_SITE_RHS = 16 * 66 + 15 * 6  # 1146
-LINK_BYTES_F32 = {"full": 16 * 72, "r14": 8 * 72 + 8 * 56, "r13": 8 * 72 + 8 * 52}  # 1152, 1024, 992
+LINK_BYTES_F32 = {"full": 16 * 72, "r14": 8 * 72 + 8 * 56, "r13": 8 * 72 + 8 * 52,
+                  "r9": 8 * 72 + 8 * 36}  # 1152, 1024, 992, 864
 VEC_BYTES_F32 = 24  # one colour vector, 3 complex FP32 numbers
 
 MI355X_HBM_GBPS = 8000.0

@@ -63,10 +63,11 @@ def test_links_bytes(H):
     assert H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_R14) == 256 + 2 * 128 * Vh * 8
     # r13: 8 U slots of 18 reals, 8 Naik slots of 13, four bytes each
     assert H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_R13) == 256 + 2 * (8 * 18 + 8 * 13) * Vh * 4
+    assert H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_R9) == 256 + 2 * (8 * 18 + 8 * 9) * Vh * 4
     # r14 is an FP32 format; odd or small extents are rejected
     assert H.hisq_links_bytes(L, H.PREC_F64, H.NAIK_R14) == 0
     assert H.hisq_links_bytes(L, H.PREC_F64, H.NAIK_R13) == 0
-    assert H.hisq_links_bytes(L, H.PREC_F32, 3) == 0
+    assert H.hisq_links_bytes(L, H.PREC_F32, 4) == 0
     assert H.hisq_links_bytes((8, 8, 8, 7), H.PREC_F64, H.NAIK_FULL) == 0
     assert H.hisq_links_bytes((2, 8, 8, 8), H.PREC_F64, H.NAIK_FULL) == 0
 

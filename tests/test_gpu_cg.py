@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 
 def _setup(H, L, eps, seed, n, sseed):
     U, N = W.make_links(L, eps, seed)
-    links = H.Links(L, dev(U), dev(N), r13=True)
+    links = H.Links(L, dev(U), dev(N), r13=True, r9=True)
     b = W.make_sources(L, n, sseed)
     return U, N, links, b
 
@@ -48,7 +48,7 @@ def test_config1_fp64_8x4():
 
 
 @pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14"),
-                                       ("mixed", "r13")])
+                                       ("mixed", "r13"), ("mixed", "r9")])
 @pytest.mark.parametrize("n", [1, 3, 4, 8])
 def test_bundles_vs_lapack(mode, naik, n):
     """4^4 (wrap aliasing): every rhs against LAPACK's dense solve."""
@@ -56,7 +56,7 @@ def test_bundles_vs_lapack(mode, naik, n):
     L, m = (4, 4, 4, 4), 0.05
     U, N, links, b = _setup(H, L, 0.3, 21, n, 22 + n)
     md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
-    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13}.get(naik, H.NAIK_FULL)
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}.get(naik, H.NAIK_FULL)
     x, status, info = H.solve(links, m, dev(b), mode=md, naik=nk)
     say(mode, naik, n, info["iters"], info["reliable_updates"])
     assert status == H.HISQ_OK
@@ -68,14 +68,14 @@ def test_bundles_vs_lapack(mode, naik, n):
 
 
 @pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "full"), ("mixed", "r14"),
-                                       ("mixed", "r13")])
+                                       ("mixed", "r13"), ("mixed", "r9")])
 def test_medium_lattice_small_mass(mode, naik):
     """16^3 x 4 (ragged tiles in every tile shape), m = 0.01, n = 5."""
     H = gpu_lib()
     L, m, n = (16, 16, 16, 4), 0.01, 5
     U, N, links, b = _setup(H, L, 0.3, 31, n, 32)
     md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
-    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13}.get(naik, H.NAIK_FULL)
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}.get(naik, H.NAIK_FULL)
     x, status, info = H.solve(links, m, dev(b), mode=md, naik=nk)
     say(mode, naik, info["iters"], info["reliable_updates"], info["rel_true_res"])
     assert status == H.HISQ_OK
@@ -233,3 +233,40 @@ def test_lds_staged_solve_matches_unstaged():
     assert np.array_equal(host(x0), host(x1))
     res = oracle.residual(L, U, N, m, b, host(x1))
     assert res.max() <= 1e-10
+
+
+def test_wide_staged_tile_with_unstaged_kernels():
+    """A forced LDS-staged FP32 Dslash tile of 384 threads (6 rhs, 3 per
+    thread, 16 staged rows of a 24 x 16 x 8 x 4 lattice) is wider than the
+    p-update and batched kernels are built for: those fall back to an unstaged
+    tile, the single solve still reports the staged tile, and single and
+    batched mixed-precision solves converge."""
+    H = gpu_lib()
+    import torch
+    m = 0.05
+    L, n = (24, 16, 8, 4), 6
+    U, N, links, b = _setup(H, L, 0.3, 71, n, 72)
+    L2, n2 = (8, 8, 8, 4), 3
+    U2, N2, links2, b2 = _setup(H, L2, 0.3, 73, n2, 74)
+    bd, bd2 = dev(b), dev(b2)
+    try:
+        H.hisq_set_tuning(1, 3, 64, 3, 16)
+        x, s, info = H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        say("wide staged single", info["block_size"], info["stage_rows"], info["iters"])
+        assert s == H.HISQ_OK
+        assert info["block_size"] == 16 * 12 * 2 and info["stage_rows"] == 16
+        assert oracle.residual(L, U, N, m, b, host(x)).max() <= 1e-10
+        xs = [torch.empty_like(bd), torch.empty_like(bd2)]
+        probs = [H.Problem(H.geom(Lq), m, nq, lq.f64.data_ptr(),
+                           lq.packed(H.PREC_F32, H.NAIK_R14).data_ptr(), bq.data_ptr(),
+                           xq.data_ptr())
+                 for Lq, nq, lq, bq, xq in ((L, n, links, bd, xs[0]), (L2, n2, links2, bd2, xs[1]))]
+        p = H.hisq_default_params(mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        ws = H.empty_bytes(H.hisq_batched_workspace_bytes(probs, H.MODE_MIXED))
+        s, infos = H.hisq_cg_solve_batched(probs, p, ws)
+        say("wide staged batched", infos[0].block_size)
+        assert s == H.HISQ_OK and 64 <= infos[0].block_size <= 256
+        for Lq, Uq, Nq, bq, xq in ((L, U, N, b, xs[0]), (L2, U2, N2, b2, xs[1])):
+            assert oracle.residual(Lq, Uq, Nq, m, bq, host(xq)).max() <= 1e-10
+    finally:
+        H.hisq_set_tuning(0)

@@ -22,7 +22,7 @@ _cache = {}
 def _links(H, L):
     if L not in _cache:
         U, N = W.make_links(L, 0.3, 7 + sum(L))
-        _cache[L] = (U, N, H.Links(L, dev(U), dev(N), r13=True))
+        _cache[L] = (U, N, H.Links(L, dev(U), dev(N), r13=True, r9=True))
     return _cache[L]
 
 
@@ -76,11 +76,11 @@ def test_dslash_f64_all_tiles(L, n):
 
 @pytest.mark.parametrize("L", LATTICES)
 @pytest.mark.parametrize("n", [1, 2, 4, 6, 7, 8])
-@pytest.mark.parametrize("naik", ["full", "r14", "r13"])
+@pytest.mark.parametrize("naik", ["full", "r14", "r13", "r9"])
 def test_dslash_f32_all_tiles(L, n, naik):
     H = gpu_lib()
     U, N, links = _links(H, L)
-    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13}.get(naik, H.NAIK_FULL)
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}.get(naik, H.NAIK_FULL)
     for parity in (0, 1):
         v = _source(L, n, 200 + n + parity).astype(np.complex64)
         want = oracle.dslash_eo(L, U, N, v.astype(np.complex128), parity)
@@ -131,10 +131,10 @@ def test_dslash_autotuned_and_bundle_independence():
         assert np.array_equal(single[:, :, 0], got[:, :, k])
 
 
-@pytest.mark.parametrize("naik", ["r14", "r13"])
+@pytest.mark.parametrize("naik", ["r14", "r13", "r9"])
 def test_pack_rejects_non_unitary_naik(naik):
     H = gpu_lib()
-    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_R13
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}[naik]
     L = (4, 4, 4, 4)
     U, N = W.make_links(L, 0.3, 5)
     N = N.copy()
@@ -153,7 +153,7 @@ def test_dslash_headline_lattice_sampled_sites():
     H = gpu_lib()
     L = (48, 48, 48, 12)
     U, N = W.make_links(L, 0.2, W.links_seed(3))
-    links = H.Links(L, dev(U), dev(N), r13=True)
+    links = H.Links(L, dev(U), dev(N), r13=True, r9=True)
     v = W.make_sources(L, 8, W.sources_seed(3))
     v32 = v.astype(np.complex64)
     rng = np.random.default_rng(9)
@@ -164,7 +164,7 @@ def test_dslash_headline_lattice_sampled_sites():
     ref64 = H.dslash(links, 1, dev(v), H.PREC_F64)
     assert rel_l2_per_rhs(host(ref64)[sites // 2], oracle.dslash_sites(L, U, N, v, 1, sites)) <= 1e-13
     H.hisq_set_tuning(0)
-    for nk in (H.NAIK_FULL, H.NAIK_R14, H.NAIK_R13):
+    for nk in (H.NAIK_FULL, H.NAIK_R14, H.NAIK_R13, H.NAIK_R9):
         for lay in (H.LAYOUT_SITE, H.LAYOUT_COLOUR):
             say("headline", nk, lay)
             g = _apply(H, links, 1, v32, H.PREC_F32, nk, lay).astype(np.complex128)
@@ -199,7 +199,8 @@ def test_dslash_lds_staged_tiles(L, n):
     U, N, links = _links(H, L)
     ran = 0
     for prec, nk, tol in ((H.PREC_F64, H.NAIK_FULL, 1e-13), (H.PREC_F32, H.NAIK_FULL, 1e-6),
-                          (H.PREC_F32, H.NAIK_R14, 1e-6), (H.PREC_F32, H.NAIK_R13, 1e-6)):
+                          (H.PREC_F32, H.NAIK_R14, 1e-6), (H.PREC_F32, H.NAIK_R13, 1e-6),
+                          (H.PREC_F32, H.NAIK_R9, 1e-6)):
         for parity in (0, 1):
             v = _source(L, n, 500 + n + parity)
             if prec == H.PREC_F32:
@@ -220,3 +221,17 @@ def test_dslash_lds_staged_tiles(L, n):
                         assert np.array_equal(got, plain), (nr, R, order)
                         ran += 1
     assert ran > 0
+
+
+def test_pack_r9_rejects_mixed_naik_scales():
+    """r9 stores one scale for the whole field: Naik links that are multiples of
+    U(3) matrices with different scales are reported, not silently rescaled."""
+    H = gpu_lib()
+    L = (4, 4, 4, 4)
+    U, N = W.make_links(L, 0.3, 5)
+    N = N.copy()
+    N[1, 3] *= 1.5
+    buf = H.empty_bytes(H.hisq_links_bytes(L, H.PREC_F32, H.NAIK_R9))
+    with pytest.raises(H.HisqError) as e:
+        H.hisq_pack_links(L, dev(U), dev(N), H.PREC_F32, H.NAIK_R9, buf)
+    assert e.value.code == H.HISQ_EPACK and "scale" in str(e.value)

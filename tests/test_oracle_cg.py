@@ -142,3 +142,28 @@ def test_r13_roundtrip_and_relation_to_r14():
     assert np.allclose(np.exp(1j * P[:, 12]), np.linalg.det(Q), atol=1e-13)
     _, err = oracle.r13_pack(Z)
     assert err > 1e-3
+
+
+def test_r9_roundtrip():
+    """r9 keeps one scale and a Hermitian H per Naik matrix: exact for the
+    synthetic links (N = -(1/24) UUU, s = 1/24) and for random U(3) matrices
+    times one scale; a general matrix or mixed scales are reported."""
+    L = (4, 4, 4, 4)
+    U, N = W.make_links(L, 0.3, 102)
+    P, s, err, spread = oracle.r9_pack(N[:, :40])
+    assert abs(s - 1.0 / 24.0) <= 1e-14 and spread <= 1e-13 and err <= 1e-12
+    assert np.abs(oracle.r9_unpack(P, s) - N[:, :40]).max() <= 1e-13
+    H = P.reshape(-1, 9)
+    # the decoded matrix is s times a unitary one
+    Wm = oracle.r9_unpack(P, 1.0).reshape(-1, 3, 3)
+    assert np.abs(Wm @ Wm.conj().transpose(0, 2, 1) - np.eye(3)).max() <= 1e-13
+    rng = np.random.default_rng(7)
+    Z = rng.standard_normal((12, 3, 3)) + 1j * rng.standard_normal((12, 3, 3))
+    Q, _ = np.linalg.qr(Z)
+    P, s, err, spread = oracle.r9_pack(0.37 * Q)
+    assert abs(s - 0.37) <= 1e-13 and err <= 1e-12
+    _, _, err, _ = oracle.r9_pack(Z)
+    assert err > 1e-3
+    _, _, _, spread = oracle.r9_pack(np.concatenate([Q[:6], 2 * Q[6:]]))
+    assert spread > 0.4
+    assert H.shape[1] == 9
