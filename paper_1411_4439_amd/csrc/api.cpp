@@ -203,17 +203,16 @@ bool t_order_ok(const Lat& lat, int G, int bs, int order);
 // The tile of a kernel without LDS staging (the p-update, the batched
 // kernels): a staged Dslash tile may hold up to kMaxBlockLds threads, more
 // than those kernels are built for, so it falls back to 128 threads.
-Tile unstaged(const Tile& t, const Lat& lat)
+Tile unstaged(const Tile& t)
 {
     if (t.rows == 0 && t.bs <= kMaxBlock) return t;
-    (void)lat;
     return Tile{t.nr, 128, t.remap, 0};
 }
 
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStream_t s)
 {
     if (pupdate_flat_ok(n)) return launch_pupdate_flat_f64(n, a, s);
-    Tile u = unstaged(t, a.lat);
+    Tile u = unstaged(t);
     if (!t_order_ok(a.lat, n / u.nr, u.bs, u.remap)) u.remap = 1;
     return launch_pupdate_f64(n, u, a, s);
 }
@@ -221,7 +220,7 @@ hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<double>& a, hipStr
 hipError_t launch_pup(int n, const Tile& t, const PupdateArgs<float>& a, hipStream_t s)
 {
     if (pupdate_flat_ok(n)) return launch_pupdate_flat_f32(n, a, s);
-    Tile u = unstaged(t, a.lat);
+    Tile u = unstaged(t);
     if (!t_order_ok(a.lat, n / u.nr, u.bs, u.remap)) u.remap = 1;
     return launch_pupdate_f32(n, u, a, s);
 }
@@ -904,7 +903,7 @@ int Engine::run(hisq_info* infos)
         size_t big = 0;
         for (size_t j = 1; j < P.size(); ++j)
             if (P[j].lat.Vh * P[j].n > P[big].lat.Vh * P[big].n) big = j;
-        batch_bs = unstaged(mixed ? P[big].t32 : P[big].t64, P[big].lat).bs;
+        batch_bs = unstaged(mixed ? P[big].t32 : P[big].t64).bs;
         static thread_local std::vector<char> tabbuf;
         tabbuf.resize(std::max(sizeof(BatchTable<double>), sizeof(BatchTable<float>)));
         rc = mixed ? upload_table<float>(tabbuf.data()) : upload_table<double>(tabbuf.data());
