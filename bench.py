@@ -16,7 +16,7 @@ The JSON line reports
   roofline       the dominant kernel's achieved GB/s against 8 TB/s,
   cg             time-to-solution of the step against 8 sequential FP64 1-rhs
                  solves of the same sources (same GPU), iterations, residuals,
-  dslash_sweep   standalone Dslash GB/s for n = 1, 2, 4, 8 (FP64, FP32, r14),
+  dslash_sweep   standalone Dslash GB/s for n = 1, 2, 4, 8 (FP64, FP32, r14, r13, r9),
   cpu_baseline   the FP64 CPU oracle's Dslash on the host cores (a bounded sample).
 """
 from __future__ import annotations
@@ -261,8 +261,6 @@ def main():
 
     if not args.no_sweep:
         sweep = {}
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
         # the solver's colour-major field order, plus the caller's site-major
         # order at the largest bundle for comparison
         cases = [(prec, nk2, tag, nn, H.LAYOUT_COLOUR)
@@ -274,29 +272,28 @@ def main():
                  for nn in (1, 2, 4, 8)]
         cases.append((H.PREC_F32, H.NAIK_R14, "f32_r14_sitemajor", n, H.LAYOUT_SITE))
         for prec, nk2, tag, nn, lay in cases:
-            if True:
-                dt = torch.complex128 if prec == H.PREC_F64 else torch.complex64
-                vin = bd[:, :, :nn].to(dt)
-                if lay == H.LAYOUT_COLOUR:
-                    vin = vin.permute(1, 0, 2)
-                vin = vin.contiguous()
-                vout = torch.empty_like(vin)
-                packed = links.packed(prec, nk2)
-                for _ in range(10):
-                    H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
-                # 100 timed launches, each between its own pair of events; median
-                evs = [torch.cuda.Event(enable_timing=True) for _ in range(101)]
-                evs[0].record(stream)
-                for r in range(100):
-                    H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
-                    evs[r + 1].record(stream)
-                evs[-1].synchronize()
-                ms = float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(100)]))
-                scale = 2 if prec == H.PREC_F64 else 1
-                kname = {H.NAIK_R14: "r14", H.NAIK_R13: "r13", H.NAIK_R9: "r9"}.get(nk2, "full")
-                byt = Vh * scale * (R.LINK_BYTES_F32[kname] + 2 * vec_b * nn)
-                sweep["%s_n%d" % (tag, nn)] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
-                                               "GFlops": round(Vh * R.FLOPS_PER_SITE_RHS * nn / ms / 1e6, 1)}
+            dt = torch.complex128 if prec == H.PREC_F64 else torch.complex64
+            vin = bd[:, :, :nn].to(dt)
+            if lay == H.LAYOUT_COLOUR:
+                vin = vin.permute(1, 0, 2)
+            vin = vin.contiguous()
+            vout = torch.empty_like(vin)
+            packed = links.packed(prec, nk2)
+            for _ in range(10):
+                H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
+            # 100 timed launches, each between its own pair of events; median
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(101)]
+            evs[0].record(stream)
+            for r in range(100):
+                H.hisq_dslash(L, 1, nn, prec, nk2, lay, packed, vin, vout)
+                evs[r + 1].record(stream)
+            evs[-1].synchronize()
+            ms = float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(100)]))
+            scale = 2 if prec == H.PREC_F64 else 1
+            kname = {H.NAIK_R14: "r14", H.NAIK_R13: "r13", H.NAIK_R9: "r9"}.get(nk2, "full")
+            byt = Vh * scale * (R.LINK_BYTES_F32[kname] + 2 * vec_b * nn)
+            sweep["%s_n%d" % (tag, nn)] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
+                                           "GFlops": round(Vh * R.FLOPS_PER_SITE_RHS * nn / ms / 1e6, 1)}
         result["dslash_sweep"] = sweep
         log("sweep", json.dumps(sweep))
 
