@@ -22,8 +22,10 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * Geometry   hisq_geom.L = (L0, L1, L2, L3); every L_mu must be even and >= 4
- *            (else HISQ_EGEOM).  V = L0 L1 L2 L3, Vh = V/2.
+ * Geometry   hisq_geom.L = (L0, L1, L2, L3); every L_mu must be even and >= 4,
+ *            and Vh * 144 < 2^31 (packed links use 32-bit offsets within a
+ *            parity block: up to about 96^3 x 24), else HISQ_EGEOM.
+ *            V = L0 L1 L2 L3, Vh = V/2.
  * Sites      s = x0 + L0*(x1 + L1*(x2 + L2*x3)); parity of s = (x0+x1+x2+x3) mod 2;
  *            even means parity 0.
  * Links      canonical input: [4][V][3][3] complex128 (mu, site, row, col),
@@ -63,7 +65,7 @@ extern "C" {
 
 #define HISQ_OK 0
 #define HISQ_EINVAL (-1)      /* null pointer, n outside 1..8, tol <= 0, bad enum   */
-#define HISQ_EGEOM (-2)       /* an extent odd or < 4                               */
+#define HISQ_EGEOM (-2)       /* an extent odd or < 4, or the lattice too large     */
 #define HISQ_EWORKSPACE (-3)  /* workspace smaller than hisq_workspace_bytes()      */
 #define HISQ_EPACK (-4)       /* r14/r13 round-trip error above 1e-6 |N| (not s*U(3)) */
 #define HISQ_EHIP (-5)        /* a HIP runtime call failed                           */

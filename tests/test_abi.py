@@ -166,3 +166,20 @@ def test_solver_refuses_host_tensors(H):
     with pytest.raises(ValueError):
         H.hisq_dslash(L, 0, 1, H.PREC_F64, H.NAIK_FULL, H.LAYOUT_SITE,
                       torch.zeros(16, dtype=torch.uint8), b, b)
+
+
+def test_lattice_size_limit(H):
+    """Packed links are indexed with 32-bit offsets per parity block (144
+    complex numbers per site): a lattice with V/2 * 144 >= 2^31 is refused
+    before any launch, and the largest production-style shapes below it are
+    accepted."""
+    lib = H._lib
+    fake = ctypes.c_void_p(0x1000)
+    big = H.geom((128, 128, 128, 16))          # V/2 * 144 = 2.4e9
+    rc = lib.hisq_dslash(ctypes.byref(big), 0, 1, H.PREC_F64, H.NAIK_FULL, 0, fake, fake, fake, None)
+    assert rc == H.HISQ_EGEOM and "too large" in H.hisq_last_error()
+    assert H.hisq_links_bytes((128, 128, 128, 16), H.PREC_F32, H.NAIK_R14) == 0
+    for L in ((96, 96, 96, 24), (64, 64, 64, 16)):
+        V = L[0] * L[1] * L[2] * L[3]
+        assert V // 2 * 144 < 2 ** 31
+        assert H.hisq_links_bytes(L, H.PREC_F64, H.NAIK_FULL) >= 2 * (V // 2) * 16 * 9 * 16

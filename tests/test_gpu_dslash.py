@@ -235,3 +235,33 @@ def test_pack_r9_rejects_mixed_naik_scales():
     with pytest.raises(H.HisqError) as e:
         H.hisq_pack_links(L, dev(U), dev(N), H.PREC_F32, H.NAIK_R9, buf)
     assert e.value.code == H.HISQ_EPACK and "scale" in str(e.value)
+
+
+def test_dslash_free_field_64x16_all_storages():
+    """The paper's production lattice size (64^3 x 16, Vh = 2 097 152, three
+    times the headline volume): with unit U and N = -1/24, plane waves are
+    eigenvectors with lambda = 2i sum(sin p - sin 3p / 24), a property that
+    holds at any size.  A two-rhs bundle of two momenta through the FP64, FP32,
+    r14, r13 and r9 Dslash in the colour-major order the solver uses."""
+    H = gpu_lib()
+    import torch
+    L, c = (64, 64, 64, 16), -1.0 / 24.0
+    U, N = W.free_links(L, c)
+    links = H.Links(L, dev(U), dev(N), r13=True, r9=True)
+    del U, N
+    ks = [(1, 2, 3, 1), (63, 5, 32, 7)]
+    vo = np.concatenate([W.to_half(W.plane_wave(L, k, [1.0, -0.5j, 0.25]), L, 1) for k in ks], axis=2)
+    ve = np.concatenate([W.to_half(W.plane_wave(L, k, [1.0, -0.5j, 0.25]), L, 0) for k in ks], axis=2)
+    lam = np.array([2j * sum(np.sin(2 * np.pi * k[mu] / L[mu]) + c * np.sin(6 * np.pi * k[mu] / L[mu])
+                             for mu in range(4)) for k in ks])
+    want = vo * lam[None, None, :]
+    ved = torch.from_numpy(np.ascontiguousarray(ve.transpose(1, 0, 2))).cuda()
+    for prec, nk, tol in ((H.PREC_F64, H.NAIK_FULL, 1e-13), (H.PREC_F32, H.NAIK_FULL, 1e-6),
+                          (H.PREC_F32, H.NAIK_R14, 1e-6), (H.PREC_F32, H.NAIK_R13, 1e-6),
+                          (H.PREC_F32, H.NAIK_R9, 1e-6)):
+        vin = ved if prec == H.PREC_F64 else ved.to(torch.complex64)
+        got = H.dslash(links, 1, vin, prec, nk, layout=H.LAYOUT_COLOUR)
+        got = np.ascontiguousarray(host(got).transpose(1, 0, 2)).astype(np.complex128)
+        err = rel_l2_per_rhs(got, want)
+        say("64^3x16 free field", prec, nk, err)
+        assert err <= tol, (prec, nk, err)
