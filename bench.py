@@ -58,9 +58,14 @@ def parse():
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", default="4,3,4",
-                    help="Dslash tile of the solve: 'rhs_per_thread,tile_order,stage_rows' "
-                         "(the autotuner's pick for this workload, pinned so that every run and "
-                         "every counter profile times the same kernel) or 'auto'")
+                    help="tile of the solve's D_oe Dslash (and p-update): "
+                         "'rhs_per_thread,tile_order,stage_rows' (the autotuner's pick for this "
+                         "workload, pinned so that every run and every counter profile times the "
+                         "same kernels) or 'auto' (autotune both Dslash kernels)")
+    ap.add_argument("--tile-eo", default="2,256,3,0",
+                    help="tile of the D_eo Dslash with the CG epilogue: "
+                         "'rhs_per_thread,block_size,tile_order,stage_rows' (the autotuner's pick), "
+                         "used unless --tile is 'auto'")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 1 GiB device-to-device copies (the reference kernel "
                          "that scales hardware byte counters)")
@@ -130,7 +135,9 @@ def main():
     nr = order = rows = 0
     if args.tile != "auto":
         nr, order, rows = (int(v) for v in args.tile.split(","))
+        eo_tile = tuple(int(v) for v in args.tile_eo.split(","))
         H.hisq_set_tuning(1, nr, 64, order, rows)
+        H.hisq_set_tuning_eo(*eo_tile)
     ws = H.empty_bytes(H.hisq_workspace_bytes(L, n, H.MODE_MIXED))
     x = torch.empty_like(bd)
     stream = torch.cuda.current_stream()
@@ -191,8 +198,9 @@ def main():
     else:
         dom = ("dslash_oe_norm", gbps_oe, bytes_oe, avg_ms[1])
     iters = infos[-1]["iters"]
-    tile = "nr=%d bs=%d order=%d rows=%d" % (infos[-1]["rhs_per_thread"], infos[-1]["block_size"],
-                                             infos[-1]["tile_order"], infos[-1]["stage_rows"])
+    pre = "eo_" if dom[0] == "dslash_eo_cg_epilogue" else ""
+    tile = "nr=%d bs=%d order=%d rows=%d" % tuple(
+        infos[-1][pre + f] for f in ("rhs_per_thread", "block_size", "tile_order", "stage_rows"))
     workload = ("HISQ even-odd CG, mixed FP32/FP64, %s Naik, %dx%dx%dx%d, %d rhs, m=%g"
                 % (nk, L[0], L[1], L[2], L[3], n, m))
     traffic, traffic_src = measured_traffic(dom[0], workload, tile)
@@ -232,9 +240,12 @@ def main():
                "mixed_seconds_graph": round(min(graph_s), 4), "iters": iters,
                "reliable_updates": infos[-1]["reliable_updates"],
                "rel_true_res_max": max(infos[-1]["rel_true_res"]),
-               "tile": {"rhs_per_thread": infos[-1]["rhs_per_thread"],
-                        "block": infos[-1]["block_size"], "order": infos[-1]["tile_order"],
-                        "stage_rows": infos[-1]["stage_rows"]}},
+               "tile_oe": {"rhs_per_thread": infos[-1]["rhs_per_thread"],
+                           "block": infos[-1]["block_size"], "order": infos[-1]["tile_order"],
+                           "stage_rows": infos[-1]["stage_rows"]},
+               "tile_eo": {"rhs_per_thread": infos[-1]["eo_rhs_per_thread"],
+                           "block": infos[-1]["eo_block_size"], "order": infos[-1]["eo_tile_order"],
+                           "stage_rows": infos[-1]["eo_stage_rows"]}},
     }
     # the comparison solver and the standalone sweep use the autotuner's tiles
     H.hisq_set_tuning(0)
@@ -324,6 +335,7 @@ def main():
         ee, eo = dev(eta_e), dev(eta_o)
         if args.tile != "auto":
             H.hisq_set_tuning(1, nr, 64, order, rows)
+            H.hisq_set_tuning_eo(*eo_tile)
         wsf = H.empty_bytes(H.hisq_trace_workspace_bytes(L, n, H.MODE_MIXED))
         H.solve_full(links, m, ee, eo, mode=H.MODE_MIXED, naik=naik, ws=wsf)  # warm
         torch.cuda.synchronize()

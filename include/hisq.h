@@ -123,10 +123,14 @@ typedef struct {
     int32_t reliable_updates;            /* FP64 true-residual recomputations           */
     int32_t polls;                       /* host polls                                  */
     int32_t total_iters;                 /* iterations of the bundle (max over rhs)     */
-    int32_t block_size;                  /* tuned work-group size of the Dslash         */
-    int32_t rhs_per_thread;              /* tuned rhs tile of the Dslash                */
+    int32_t block_size;                  /* tuned work-group size of the D_oe Dslash    */
+    int32_t rhs_per_thread;              /* tuned rhs tile of the D_oe Dslash           */
     int32_t tile_order;                  /* tuned work-group -> tile order (0..3)       */
     int32_t stage_rows;                  /* tuned LDS-staged x-rows per tile (0: none)  */
+    int32_t eo_block_size;               /* the same four for the D_eo Dslash with the  */
+    int32_t eo_rhs_per_thread;           /* CG epilogue (equal to the above in batched  */
+    int32_t eo_tile_order;               /* solves)                                     */
+    int32_t eo_stage_rows;
     int32_t reserved;
     double seconds;                      /* host wall time of the solve                 */
     double kernel_ms[HISQ_K_COUNT];      /* profile = 1: summed event time per class    */
@@ -304,6 +308,18 @@ int hisq_trace_estimate(const hisq_geom* g, double mass, int nrhs, const hisq_pa
  * out-of-range values.
  */
 int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order, int stage_rows);
+
+/*
+ * In a single solve the D_eo half-Dslash with the CG epilogue (it also reads
+ * p, x, r and writes x, r) is tuned on its own, separately from D_oe, whose
+ * tile the p-update, the batched kernels and the FP64 residual share; both
+ * tiles are reported in hisq_info.  This call gives the D_eo kernel its own
+ * tile under tuning mode 1, with the arguments of hisq_set_tuning; until it is
+ * called, after rhs_per_thread = 0, and after every hisq_set_tuning call, that
+ * kernel takes the mode-1 tile of hisq_set_tuning.  Returns HISQ_EINVAL for
+ * out-of-range values.
+ */
+int hisq_set_tuning_eo(int rhs_per_thread, int block_size, int tile_order, int stage_rows);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* hisq_last_error(void);

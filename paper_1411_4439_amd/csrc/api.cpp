@@ -232,6 +232,8 @@ std::mutex g_tune_mu;
 std::map<std::string, Tile> g_tune_cache;
 int g_tune_mode = 0;
 int g_force_nr = 0, g_force_bs = 0, g_force_order = 1, g_force_rows = 0;
+// mode 1: a tile of its own for the D_eo kernel with the CG epilogue (nr 0: none)
+int g_force_eo_nr = 0, g_force_eo_bs = 0, g_force_eo_order = 1, g_force_eo_rows = 0;
 
 // Tile order 2 needs tiles that never straddle a time slice; order 3 needs
 // z-chunks of whole planes for each of the 8 XCDs and tiles that divide an x-y
@@ -297,10 +299,11 @@ int get_tile(const Lat& lat, int n, int prec, int nk, const DslashArgs<T>& probe
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         mode = g_tune_mode;
-        fnr = g_force_nr;
-        fbs = g_force_bs;
-        ford = g_force_order;
-        frows = g_force_rows;
+        const bool eo = epi == EPI_CG && g_force_eo_nr > 0;
+        fnr = eo ? g_force_eo_nr : g_force_nr;
+        fbs = eo ? g_force_eo_bs : g_force_bs;
+        ford = eo ? g_force_eo_order : g_force_order;
+        frows = eo ? g_force_eo_rows : g_force_rows;
     }
     if (mode == 1 && valid_nr(n, fnr)) {
         const int sbs = cm ? staged_block(lat, n, n / fnr, frows, prec) : 0;
@@ -420,7 +423,8 @@ struct Prob {
     const d2* b = nullptr;  // colour-major working copies [3][Vh][n]
     d2* x = nullptr;
     Ws w;
-    Tile t64{}, t32{};
+    Tile t64{}, t32{};    // D_oe with |t|^2 (tuned), the p-update, the FP64 residual
+    Tile t64e{}, t32e{};  // D_eo with the CG epilogue (tuned on its own)
     CgState* hs = nullptr;  // pinned host copy
     double bb[kMaxRhs] = {}, maxrr[kMaxRhs] = {};
     bool fin[kMaxRhs] = {};
@@ -532,13 +536,14 @@ struct Engine {
         DslashArgs<T> k2, k3;
         iter_args<T>(q, k1, k2, k3);
         const Tile& tile = std::is_same<T, float>::value ? q.t32 : q.t64;
+        const Tile& tile_e = std::is_same<T, float>::value ? q.t32e : q.t64e;
         const int rr = std::is_same<T, float>::value ? nk : HISQ_NAIK_FULL;
         if (evs) HIP_TRY(hipEventRecord(evs[0], st));
         HIP_TRY(launch_pup(q.n, tile, k1, st));
         if (evs) HIP_TRY(hipEventRecord(evs[1], st));
         HIP_TRY(launch_ds(EPI_NORM, q.n, rr, tile, k2, st));
         if (evs) HIP_TRY(hipEventRecord(evs[2], st));
-        HIP_TRY(launch_ds(EPI_CG, q.n, rr, tile, k3, st));
+        HIP_TRY(launch_ds(EPI_CG, q.n, rr, tile_e, k3, st));
         if (evs) HIP_TRY(hipEventRecord(evs[3], st));
         return HISQ_OK;
     }
@@ -830,10 +835,15 @@ int Engine::finish(CgState* host, hisq_info* infos, double seconds)
         if (info) {
             std::memset(info, 0, sizeof(*info));
             const Tile& t = mixed ? q.t32 : q.t64;
+            const Tile& te = mixed ? q.t32e : q.t64e;
             info->block_size = P.size() == 1 ? t.bs : batch_bs;
             info->rhs_per_thread = t.nr;
             info->tile_order = P.size() == 1 ? t.remap : 0;
             info->stage_rows = P.size() == 1 ? t.rows : 0;
+            info->eo_block_size = P.size() == 1 ? te.bs : batch_bs;
+            info->eo_rhs_per_thread = te.nr;
+            info->eo_tile_order = P.size() == 1 ? te.remap : 0;
+            info->eo_stage_rows = P.size() == 1 ? te.rows : 0;
         }
         int maxit = 0;
         for (int k = 0; k < q.n; ++k) {
@@ -895,6 +905,27 @@ int Engine::run(hisq_info* infos)
             p32.red = q.w.red;
             p32.cnt = q.w.cnt;
             if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F32, nk, p32, s, &q.t32, EPI_NORM))) return rc;
+        }
+        // the D_eo kernel with the CG epilogue, timed on the iteration's own
+        // buffers with the state re-armed (frozen, every rhs active, alpha = 0:
+        // x and r keep their values, and setup() initialises them afterwards)
+        q.t64e = q.t64;
+        q.t32e = q.t32;
+        if (P.size() == 1) {
+            HIP_TRY(launch_zero(q.w.cnt, q.w.cnt_bytes, s));
+            HIP_TRY(launch_state_reset(q.w.st, q.n, 1, s));
+            if (mixed) {
+                PupdateArgs<float> k1;
+                DslashArgs<float> k2, k3;
+                iter_args<float>(q, k1, k2, k3);
+                if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F32, nk, k3, s, &q.t32e, EPI_CG))) return rc;
+            } else {
+                PupdateArgs<double> k1;
+                DslashArgs<double> k2, k3;
+                iter_args<double>(q, k1, k2, k3);
+                if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F64, HISQ_NAIK_FULL, k3, s, &q.t64e, EPI_CG)))
+                    return rc;
+            }
         }
     }
     if ((rc = setup(host))) return rc;
@@ -1533,6 +1564,25 @@ int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order
     g_force_bs = block_size;
     g_force_order = mode == 1 ? tile_order : 1;
     g_force_rows = mode == 1 ? stage_rows : 0;
+    g_force_eo_nr = 0;
+    return HISQ_OK;
+}
+
+int hisq_set_tuning_eo(int rhs_per_thread, int block_size, int tile_order, int stage_rows)
+{
+    if (rhs_per_thread != 0) {
+        if (rhs_per_thread < 1 || rhs_per_thread > HISQ_MAX_RHS)
+            return fail(HISQ_EINVAL, "rhs_per_thread must be in 0..8");
+        if (block_size != 64 && block_size != 128 && block_size != 256)
+            return fail(HISQ_EINVAL, "block_size must be 64, 128 or 256");
+        if (tile_order < 0 || tile_order > 3) return fail(HISQ_EINVAL, "tile_order must be 0..3");
+        if (stage_rows < 0 || stage_rows > 64) return fail(HISQ_EINVAL, "stage_rows must be 0..64");
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_force_eo_nr = rhs_per_thread;
+    g_force_eo_bs = block_size;
+    g_force_eo_order = tile_order;
+    g_force_eo_rows = stage_rows;
     return HISQ_OK;
 }
 

@@ -50,7 +50,9 @@ class Info(ctypes.Structure):
                 ("reliable_updates", ctypes.c_int32), ("polls", ctypes.c_int32),
                 ("total_iters", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("rhs_per_thread", ctypes.c_int32), ("tile_order", ctypes.c_int32),
-                ("stage_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stage_rows", ctypes.c_int32), ("eo_block_size", ctypes.c_int32),
+                ("eo_rhs_per_thread", ctypes.c_int32), ("eo_tile_order", ctypes.c_int32),
+                ("eo_stage_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seconds", ctypes.c_double),
                 ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int32 * 4)]
 
@@ -63,6 +65,8 @@ class Info(ctypes.Structure):
             "total_iters": self.total_iters, "block_size": self.block_size,
             "rhs_per_thread": self.rhs_per_thread, "tile_order": self.tile_order,
             "stage_rows": self.stage_rows,
+            "eo_block_size": self.eo_block_size, "eo_rhs_per_thread": self.eo_rhs_per_thread,
+            "eo_tile_order": self.eo_tile_order, "eo_stage_rows": self.eo_stage_rows,
             "seconds": self.seconds,
             "kernel_ms": list(self.kernel_ms), "kernel_launches": list(self.kernel_launches),
         }
@@ -96,6 +100,7 @@ _sig = {
                                              ctypes.POINTER(Info), _P]),
     "hisq_set_tuning": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int]),
+    "hisq_set_tuning_eo": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "hisq_full_workspace_bytes": (ctypes.c_size_t, [_G, ctypes.c_int, ctypes.c_int]),
     "hisq_trace_workspace_bytes": (ctypes.c_size_t, [_G, ctypes.c_int, ctypes.c_int]),
     "hisq_dslash_dmu": (ctypes.c_int, [_G, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P,
@@ -233,6 +238,11 @@ def hisq_cg_solve_batched(problems, params, ws, stream=None):
 def hisq_set_tuning(mode, rhs_per_thread=0, block_size=0, tile_order=1, stage_rows=0):
     return _check(_lib.hisq_set_tuning(mode, rhs_per_thread, block_size, tile_order, stage_rows),
                   "hisq_set_tuning")
+
+
+def hisq_set_tuning_eo(rhs_per_thread=0, block_size=64, tile_order=1, stage_rows=0):
+    return _check(_lib.hisq_set_tuning_eo(rhs_per_thread, block_size, tile_order, stage_rows),
+                  "hisq_set_tuning_eo")
 
 
 def hisq_last_error():

@@ -46,7 +46,7 @@ def test_struct_layouts_match_header(H):
     assert ctypes.sizeof(H.Geom) == 16
     assert ctypes.sizeof(H.Params) == 48
     assert ctypes.sizeof(H.Problem) == 16 + 8 + 8 + 4 * 8
-    assert ctypes.sizeof(H.Info) == 8 * 4 * 2 + 8 * 8 * 2 + 8 * 4 + 8 + 4 * 8 + 4 * 4
+    assert ctypes.sizeof(H.Info) == 8 * 4 * 2 + 8 * 8 * 2 + 12 * 4 + 8 + 4 * 8 + 4 * 4
 
 
 def test_default_params(H):
@@ -156,6 +156,12 @@ def test_tuning_control(H):
     with pytest.raises(H.HisqError):
         H.hisq_set_tuning(1, 4, 64, 3, -1)
     assert H.hisq_set_tuning(1, 4, 64, 3, 8) == 0
+    assert H.hisq_set_tuning_eo(2, 256, 3, 0) == 0
+    with pytest.raises(H.HisqError):
+        H.hisq_set_tuning_eo(2, 96, 3, 0)
+    with pytest.raises(H.HisqError):
+        H.hisq_set_tuning_eo(9, 64, 3, 0)
+    assert H.hisq_set_tuning_eo(0) == 0
     assert H.hisq_set_tuning(0) == 0
 
 

@@ -270,3 +270,32 @@ def test_wide_staged_tile_with_unstaged_kernels():
             assert oracle.residual(Lq, Uq, Nq, m, bq, host(xq)).max() <= 1e-10
     finally:
         H.hisq_set_tuning(0)
+
+
+def test_separate_tile_for_the_cg_epilogue_kernel():
+    """The D_eo kernel with the CG epilogue takes a tile of its own: forced
+    (LDS-staged D_oe, unstaged 2-rhs D_eo) and autotuned, both reported in the
+    info, and the solves reach the oracle's true residual."""
+    H = gpu_lib()
+    L, m, n = (16, 16, 16, 4), 0.02, 8
+    U, N, links, b = _setup(H, L, 0.3, 81, n, 82)
+    bd = dev(b)
+    try:
+        H.hisq_set_tuning(1, 4, 64, 3, 4)
+        H.hisq_set_tuning_eo(2, 256, 3, 0)
+        x, s, info = H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        say("forced", info["block_size"], info["stage_rows"], info["eo_block_size"],
+            info["eo_rhs_per_thread"], info["iters"])
+        assert s == H.HISQ_OK
+        assert (info["rhs_per_thread"], info["stage_rows"]) == (4, 4)
+        assert (info["eo_rhs_per_thread"], info["eo_block_size"], info["eo_stage_rows"]) == (2, 256, 0)
+        assert oracle.residual(L, U, N, m, b, host(x)).max() <= 1e-10
+        H.hisq_set_tuning(0)
+        for mode in (H.MODE_MIXED, H.MODE_FP64):
+            x, s, info = H.solve(links, m, bd, mode=mode, naik=H.NAIK_R14)
+            say("autotuned", mode, info)
+            assert s == H.HISQ_OK
+            assert info["eo_block_size"] >= 64 and n % info["eo_rhs_per_thread"] == 0
+            assert oracle.residual(L, U, N, m, b, host(x)).max() <= 1e-10
+    finally:
+        H.hisq_set_tuning(0)
