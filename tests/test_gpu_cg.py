@@ -299,3 +299,26 @@ def test_separate_tile_for_the_cg_epilogue_kernel():
             assert oracle.residual(L, U, N, m, b, host(x)).max() <= 1e-10
     finally:
         H.hisq_set_tuning(0)
+
+
+def test_config2_32x8_fp64_vs_mixed_bundles():
+    """32^3 x 8, m = 0.02, complex Gaussian sources, bundles of 1, 2, 4 and 8:
+    plain FP64 against FP32 storage (r14 Naik) with FP64 reliable updates, both
+    to true residual 1e-10 (recomputed by the oracle), solutions within 1e-8
+    of each other or the a-posteriori bound."""
+    H = gpu_lib()
+    L, m = (32, 32, 32, 8), 0.02
+    U, N = W.make_links(L, 0.3, W.links_seed(2))
+    links = H.Links(L, dev(U), dev(N))
+    b8 = W.make_sources(L, 8, W.sources_seed(2))
+    for n in (1, 2, 4, 8):
+        b = np.ascontiguousarray(b8[:, :, :n])
+        x64, s64, i64 = H.solve(links, m, dev(b), mode=H.MODE_FP64)
+        xmx, smx, imx = H.solve(links, m, dev(b), mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        say("config2 n=%d" % n, "fp64", i64["iters"], "%.3f s" % i64["seconds"],
+            "mixed", imx["iters"], imx["reliable_updates"], "%.3f s" % imx["seconds"])
+        assert s64 == smx == H.HISQ_OK
+        r64 = oracle.residual(L, U, N, m, b, host(x64))
+        rmx = oracle.residual(L, U, N, m, b, host(xmx))
+        assert r64.max() <= 1e-10 and rmx.max() <= 1e-10
+        _check_solution(L, U, N, m, b, host(xmx), host(x64))
