@@ -426,7 +426,7 @@ struct Prob {
     Tile t64{}, t32{};    // D_oe with |t|^2 (tuned), the p-update, the FP64 residual
     Tile t64e{}, t32e{};  // D_eo with the CG epilogue (tuned on its own)
     CgState* hs = nullptr;  // pinned host copy
-    double bb[kMaxRhs] = {}, maxrr[kMaxRhs] = {};
+    double bb[kMaxRhs] = {};
     bool fin[kMaxRhs] = {};
     int restarts[kMaxRhs] = {};
     double rr_iter[kMaxRhs] = {};
@@ -688,7 +688,7 @@ int Engine::setup(CgState* host)
             q.bb[k] = h->aux[k];
             h->thresh[k] = tol2 * q.bb[k];
             h->rr[k] = h->rr_true[k];
-            q.maxrr[k] = h->rr[k];
+            h->rrmax[k] = h->rr[k];
             h->beta[k] = 0.0;
             h->iters[k] = 0;
             h->status[k] = HISQ_OK;
@@ -738,7 +738,7 @@ int Engine::poll_and_update(CgState* host)
                 }
             } else if (!h->active[k]) {
                 h->sel[k] = 1;  // iterated residual passed (or maxiter): check the true one
-            } else if (mixed && h->rr[k] < prm.delta * prm.delta * q.maxrr[k]) {
+            } else if (mixed && h->rr[k] < prm.delta * prm.delta * h->rrmax[k]) {
                 h->sel[k] = 1;  // reliable update
             }
             any_q = any_q || h->sel[k];
@@ -802,7 +802,7 @@ int Engine::poll_and_update(CgState* host)
                 h->beta[k] = 0.0;  // restart from the true residual
             }
             h->rr[k] = rt;
-            q.maxrr[k] = rt;
+            h->rrmax[k] = rt;
             h->active[k] = 1;
         }
         for (int k = 0; k < q.n; ++k) h->sel[k] = 0;

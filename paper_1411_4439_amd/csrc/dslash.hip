@@ -316,6 +316,7 @@ __device__ __forceinline__ void finish(CgState* st, int k, double tot, double m4
             } else {
                 st->beta[k] = tot / st->rr[k];
                 st->rr[k] = tot;
+                if (tot > st->rrmax[k]) st->rrmax[k] = tot;
                 if (tot <= st->thresh[k] || st->iters[k] >= st->maxiter) st->active[k] = 0;
             }
         }

@@ -135,6 +135,7 @@ struct CgState {
     double thresh[kMaxRhs];  // device-side masking threshold on rr
     double rr_true[kMaxRhs]; // |b - A x|^2 of the last true-residual pass
     double aux[kMaxRhs];     // |b|^2
+    double rrmax[kMaxRhs];   // largest iterated |r|^2 since the last true-residual pass
     int32_t active[kMaxRhs];
     int32_t status[kMaxRhs];
     int32_t iters[kMaxRhs];
