@@ -7,7 +7,7 @@ import pytest
 
 def gpu_lib():
     """The HIP binding; skip cleanly where no GPU is visible, fail loudly if the
-    library is missing on a GPU machine."""
+    library is missing on a machine with a GPU."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU visible")
