@@ -167,3 +167,22 @@ def test_r9_roundtrip():
     _, _, _, spread = oracle.r9_pack(np.concatenate([Q[:6], 2 * Q[6:]]))
     assert spread > 0.4
     assert H.shape[1] == 9
+
+
+def test_r9_closed_forms():
+    """r9 against closed forms: H = diag(a, b, c) decodes to s diag(e^ia, e^ib,
+    e^ic); a 2x2 block H = theta * sigma_x decodes to cos(theta) 1 + i sin(theta)
+    sigma_x; and packing s diag(e^{i phi}) recovers phi on the principal branch."""
+    s = 0.25
+    P = np.array([0.3, -1.1, 2.0, 0, 0, 0, 0, 0, 0])
+    got = oracle.r9_unpack(P[None], s)[0]
+    assert np.allclose(got, s * np.diag(np.exp(1j * P[:3])), atol=1e-15)
+    th = 0.7
+    P = np.array([0, 0, 0, th, 0, 0, 0, 0, 0])
+    want = s * np.array([[np.cos(th), 1j * np.sin(th), 0], [1j * np.sin(th), np.cos(th), 0],
+                         [0, 0, 1]])
+    assert np.allclose(oracle.r9_unpack(P[None], s)[0], want, atol=1e-15)
+    phi = np.array([0.4, -2.5, 1.9])
+    Pp, sp, err, spread = oracle.r9_pack((s * np.diag(np.exp(1j * phi)))[None])
+    assert abs(sp - s) <= 1e-15 and err <= 1e-13 and spread == 0.0
+    assert np.allclose(Pp[0, :3], phi, atol=1e-12) and np.allclose(Pp[0, 3:], 0, atol=1e-12)
