@@ -6,11 +6,13 @@ package never loads the HIP library: the two share no code.
 
 ``hisq_oracle.c`` holds the arithmetic (HISQ Dslash of eq. (3) of Kaczmarek et
 al., GPUHEP2014, the even-odd operator A = 4m^2 - D_eo D_oe, CG, the link force,
-the 14-real Naik encoding and the mu-derivatives of the Dslash); this module
-compiles it with gcc and marshals numpy arrays through ctypes.  The full-matrix
-solve and the trace estimator of eq. (2) below only chain those routines in the
-order the method states.  ``oracle.dense`` assembles the same operators as dense
-matrices for tiny lattices.
+the 14- and 13-real Naik encodings and the mu-derivatives of the Dslash); this
+module compiles it with gcc and marshals numpy arrays through ctypes.  The
+full-matrix solve and the trace estimator of eq. (2) below only chain those
+routines in the order the method states; the 9-real Naik encoding (one scale,
+a Hermitian generator) uses scipy's matrix logarithm and exponential.
+``oracle.dense`` assembles the same operators as dense matrices for tiny
+lattices.
 """
 from __future__ import annotations
 
