@@ -179,6 +179,11 @@ __device__ __forceinline__ void stage_rows(const cplx<T>* __restrict__ in, cplx<
         yy -= yy >= Ly ? Ly : 0;
         return (size_t)(plane * Ly + yy) * lat.Lh0;
     };
+    // Each thread copies its units in batches of kStageBatch: all the batch's
+    // reads are issued before the first LDS write, so a thread waits for one
+    // memory round trip per batch instead of one per unit.
+    constexpr unsigned kStageBatch = 8;
+    const unsigned nt = blockDim.x;
     if constexpr (sizeof(T) == 4) {
         if ((lat.Lh0 * NRHS) % 2 == 0) {
             // 16-byte units of two complex numbers
@@ -186,20 +191,40 @@ __device__ __forceinline__ void stage_rows(const cplx<T>* __restrict__ in, cplx<
             const unsigned total = 3u * rows * chunk;
             const f4* src = reinterpret_cast<const f4*>(in);
             f4* dst = reinterpret_cast<f4*>(lds);
-            for (unsigned u = threadIdx.x; u < total; u += blockDim.x) {
-                const unsigned cj = u / chunk, off = u - cj * chunk;
-                const unsigned c = cj / rows, j = cj - c * rows;
-                dst[u] = src[((size_t)c * lat.Vh + row_site(j)) * NRHS / 2 + off];
+            for (unsigned u0 = threadIdx.x; u0 < total; u0 += kStageBatch * nt) {
+                f4 buf[kStageBatch];
+#pragma unroll
+                for (unsigned q = 0; q < kStageBatch; ++q) {
+                    const unsigned u = u0 + q * nt;
+                    if (u < total) {
+                        const unsigned cj = u / chunk, off = u - cj * chunk;
+                        const unsigned c = cj / rows, j = cj - c * rows;
+                        buf[q] = src[((size_t)c * lat.Vh + row_site(j)) * NRHS / 2 + off];
+                    }
+                }
+#pragma unroll
+                for (unsigned q = 0; q < kStageBatch; ++q)
+                    if (u0 + q * nt < total) dst[u0 + q * nt] = buf[q];
             }
             return;
         }
     }
     const unsigned chunk = (unsigned)(lat.Lh0 * NRHS);
     const unsigned total = 3u * rows * chunk;
-    for (unsigned u = threadIdx.x; u < total; u += blockDim.x) {
-        const unsigned cj = u / chunk, off = u - cj * chunk;
-        const unsigned c = cj / rows, j = cj - c * rows;
-        lds[u] = in[((size_t)c * lat.Vh + row_site(j)) * NRHS + off];
+    for (unsigned u0 = threadIdx.x; u0 < total; u0 += kStageBatch * nt) {
+        cplx<T> buf[kStageBatch];
+#pragma unroll
+        for (unsigned q = 0; q < kStageBatch; ++q) {
+            const unsigned u = u0 + q * nt;
+            if (u < total) {
+                const unsigned cj = u / chunk, off = u - cj * chunk;
+                const unsigned c = cj / rows, j = cj - c * rows;
+                buf[q] = in[((size_t)c * lat.Vh + row_site(j)) * NRHS + off];
+            }
+        }
+#pragma unroll
+        for (unsigned q = 0; q < kStageBatch; ++q)
+            if (u0 + q * nt < total) lds[u0 + q * nt] = buf[q];
     }
 }
 
@@ -234,11 +259,32 @@ __device__ __forceinline__ int lds_neighbour(const Lat& lat, int r, int xh, int 
 // read issued before it: an even (global) step issues the next link, computes,
 // then issues the link after that and the global neighbour of four steps ahead
 // (two global slots of lookahead), and the LDS neighbour of the next step.
+// The global reads that open the pipeline (slot 0's link, the first two
+// global neighbours): issued before the work-group's staging barrier, so
+// that their latency overlaps the staging reads instead of following them.
+template <typename T, int NRHS, int NR, int NK>
+struct LdsHead {
+    cplx<T> m[9];
+    cplx<T> v0[3][NR], v1[3][NR];
+};
+
+template <typename T, int NRHS, int NR, int NK>
+__device__ __forceinline__ void lds_head(const Lat& lat, int P, int i, int g,
+                                         const cplx<T>* __restrict__ lk,
+                                         const cplx<T>* __restrict__ in, LdsHead<T, NRHS, NR, NK>& h)
+{
+    const SiteCoord sc = site_coord(lat, P, i);
+    load_link<T, NK, slot_at(0)>(lk, lat.Vh, i, h.m);
+    load_vec<T, NRHS, NR, true>(in, lat.Vh, neighbour<slot_at(0)>(lat, sc), g, h.v0);
+    load_vec<T, NRHS, NR, true>(in, lat.Vh, neighbour<slot_at(2)>(lat, sc), g, h.v1);
+}
+
 template <typename T, int NRHS, int NR, int NK>
 __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, int g, int r,
                                                 const cplx<T>* __restrict__ lk,
                                                 const cplx<T>* __restrict__ in,
                                                 const cplx<T>* lds, int rows,
+                                                const LdsHead<T, NRHS, NR, NK>& h,
                                                 cplx<T> (&acc)[3][NR], T ns)
 {
     using C = cplx<T>;
@@ -253,9 +299,15 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
     C m[2][9];
     C vg[2][3][NR];
     C vl[3][NR];
-    load_link<T, NK, slot_at(0)>(lk, Vh, i, m[0]);
-    load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(0)>(lat, sc), g, vg[0]);
-    load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(2)>(lat, sc), g, vg[1]);
+#pragma unroll
+    for (int e = 0; e < 9; ++e) m[0][e] = h.m[e];
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            vg[0][b][k] = h.v0[b][k];
+            vg[1][b][k] = h.v1[b][k];
+        }
     static_for<0, 16>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (k % 2 == 0) {
@@ -372,9 +424,11 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
     if constexpr (NK == HISQ_NAIK_R9) ns = (T)*a.naik_scale;
 
     const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
+    LdsHead<T, NRHS, NR, NK> head;
     if constexpr (ST) {
         // the tile is `rows` whole x-rows: stage them and their +-3 row halo
         static_assert(CM, "staging reads colour-major fields");
+        if (i < a.lat.Vh) lds_head<T, NRHS, NR, NK>(a.lat, a.parity, i, g, a.links, a.in, head);
         stage_rows<T, NRHS>(a.in, lds, a.lat, tile * a.rows, a.rows);
         __syncthreads();
     }
@@ -383,7 +437,7 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
         if constexpr (ST)
             dslash_site_lds<T, NRHS, NR, NK>(a.lat, a.parity, i, g,
                                               ((int)threadIdx.x / G) / a.lat.Lh0, a.links, a.in,
-                                              lds, a.rows + 6, acc, ns);
+                                              lds, a.rows + 6, head, acc, ns);
         else
             dslash_site<T, NRHS, NR, NK, CM>(a.lat, a.parity, i, g, a.links, a.in, acc, ns);
         pin_acc(acc);
