@@ -182,13 +182,32 @@ __device__ __forceinline__ void stage_rows(const cplx<T>* __restrict__ in, cplx<
     // Each thread copies its units in batches of kStageBatch: all the batch's
     // reads are issued before the first LDS write, so a thread waits for one
     // memory round trip per batch instead of one per unit.
-    constexpr unsigned kStageBatch = 8;
+    constexpr unsigned kStageBatch = 16;
     const unsigned nt = blockDim.x;
+    // unit u -> (colour c, staged row j, offset): u / chunk through a float
+    // reciprocal with a one-step correction (u < 2^16 here, so the estimate
+    // is off by at most one), c by comparisons (c < 3)
+    auto split = [rows](unsigned u, unsigned chunk, float inv, unsigned& c, unsigned& j,
+                        unsigned& off) {
+        unsigned cj = (unsigned)((float)u * inv);
+        int r = (int)u - (int)(cj * chunk);
+        if (r < 0) {
+            --cj;
+            r += (int)chunk;
+        } else if (r >= (int)chunk) {
+            ++cj;
+            r -= (int)chunk;
+        }
+        off = (unsigned)r;
+        c = (cj >= rows ? 1u : 0u) + (cj >= 2 * rows ? 1u : 0u);
+        j = cj - c * rows;
+    };
     if constexpr (sizeof(T) == 4) {
         if ((lat.Lh0 * NRHS) % 2 == 0) {
             // 16-byte units of two complex numbers
             const unsigned chunk = (unsigned)(lat.Lh0 * NRHS / 2);
             const unsigned total = 3u * rows * chunk;
+            const float inv = 1.0f / (float)chunk;
             const f4* src = reinterpret_cast<const f4*>(in);
             f4* dst = reinterpret_cast<f4*>(lds);
             for (unsigned u0 = threadIdx.x; u0 < total; u0 += kStageBatch * nt) {
@@ -197,8 +216,8 @@ __device__ __forceinline__ void stage_rows(const cplx<T>* __restrict__ in, cplx<
                 for (unsigned q = 0; q < kStageBatch; ++q) {
                     const unsigned u = u0 + q * nt;
                     if (u < total) {
-                        const unsigned cj = u / chunk, off = u - cj * chunk;
-                        const unsigned c = cj / rows, j = cj - c * rows;
+                        unsigned c, j, off;
+                        split(u, chunk, inv, c, j, off);
                         buf[q] = src[((size_t)c * lat.Vh + row_site(j)) * NRHS / 2 + off];
                     }
                 }
@@ -211,14 +230,15 @@ __device__ __forceinline__ void stage_rows(const cplx<T>* __restrict__ in, cplx<
     }
     const unsigned chunk = (unsigned)(lat.Lh0 * NRHS);
     const unsigned total = 3u * rows * chunk;
+    const float inv = 1.0f / (float)chunk;
     for (unsigned u0 = threadIdx.x; u0 < total; u0 += kStageBatch * nt) {
         cplx<T> buf[kStageBatch];
 #pragma unroll
         for (unsigned q = 0; q < kStageBatch; ++q) {
             const unsigned u = u0 + q * nt;
             if (u < total) {
-                const unsigned cj = u / chunk, off = u - cj * chunk;
-                const unsigned c = cj / rows, j = cj - c * rows;
+                unsigned c, j, off;
+                split(u, chunk, inv, c, j, off);
                 buf[q] = in[((size_t)c * lat.Vh + row_site(j)) * NRHS + off];
             }
         }
