@@ -15,7 +15,7 @@ def _backward(H, L, U, N, m, x, phi, mode=0, naik=0, tol=1e-10):
     import torch
     n = x.shape[2]
     V = W.volume(L)
-    links = H.Links(L, dev(U), dev(N))
+    links = H.Links(L, dev(U), dev(N), r13=True, r9=True)
     gU = torch.empty((4, V, 3, 3), dtype=torch.complex128, device="cuda")
     gN = torch.empty_like(gU)
     gm = torch.zeros((), dtype=torch.float64, device="cuda")
@@ -46,6 +46,26 @@ def test_force_matches_oracle(L, mode):
     assert np.linalg.norm(gN - GN) <= tol * np.linalg.norm(GN)
     assert abs(gm - dm) <= tol * abs(dm)
     assert np.linalg.norm(gb - y) <= tol * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("naik", ["r14", "r13", "r9"])
+def test_force_mixed_compressed_naik(naik):
+    """Mixed-precision backward with compressed FP32 Naik links: the adjoint
+    solve runs on the compressed links, the force in FP64."""
+    H = gpu_lib()
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}[naik]
+    L, m, n = (4, 4, 4, 4), 0.05, 2
+    U, N = W.make_links(L, 0.3, 211)
+    eta = W.make_sources(L, n, 212)
+    phi = W.make_sources(L, n, 213)
+    x, _ = oracle.cg(L, U, N, m, eta, tol=1e-13)
+    y, _ = oracle.cg(L, U, N, m, phi, tol=1e-13)
+    GU, GN, dm = oracle.force(L, U, N, m, x, y)
+    gU, gN, gm, gb = _backward(H, L, U, N, m, x, phi, mode=H.MODE_MIXED, naik=nk, tol=1e-12)
+    say(naik, np.linalg.norm(gU - GU) / np.linalg.norm(GU))
+    assert np.linalg.norm(gU - GU) <= 1e-7 * np.linalg.norm(GU)
+    assert np.linalg.norm(gN - GN) <= 1e-7 * np.linalg.norm(GN)
+    assert abs(gm - dm) <= 1e-7 * abs(dm)
 
 
 def test_autograd_finite_differences():

@@ -169,11 +169,12 @@ def test_batched_equals_separate_solves():
     specs = [((8, 8, 8, 4), 3, 0.05), ((6, 6, 6, 4), 5, 0.01), ((8, 8, 4, 4), 8, 0.05),
              ((4, 4, 4, 4), 1, 0.1)]
     for mode, naik in ((H.MODE_MIXED, H.NAIK_FULL), (H.MODE_MIXED, H.NAIK_R14),
+                       (H.MODE_MIXED, H.NAIK_R13), (H.MODE_MIXED, H.NAIK_R9),
                        (H.MODE_FP64, H.NAIK_FULL)):
         probs, keep, refs = [], [], []
         for j, (L, n, m) in enumerate(specs):
             U, N = W.make_links(L, 0.3, 90 + j)
-            links = H.Links(L, dev(U), dev(N))
+            links = H.Links(L, dev(U), dev(N), r13=True, r9=True)
             b = W.make_sources(L, n, 95 + j)
             bd = dev(b)
             x = torch.empty_like(bd)

@@ -27,15 +27,16 @@ def test_dslash_dmu_vs_oracle(L, n):
             assert rel_l2_per_rhs(got, want) <= 1e-13, (nder, par)
 
 
-@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "r14")])
+@pytest.mark.parametrize("mode,naik", [("fp64", "full"), ("mixed", "r14"), ("mixed", "r13"),
+                                       ("mixed", "r9")])
 def test_solve_full_vs_lapack(mode, naik):
     H = gpu_lib()
     L, m, n = (4, 4, 4, 4), 0.1, 3
     U, N = W.make_links(L, 0.3, 90)
-    links = H.Links(L, dev(U), dev(N))
+    links = H.Links(L, dev(U), dev(N), r13=True, r9=True)
     b_e, b_o = W.make_noise(L, n, 91, "gauss")
     md = H.MODE_MIXED if mode == "mixed" else H.MODE_FP64
-    nk = H.NAIK_R14 if naik == "r14" else H.NAIK_FULL
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}.get(naik, H.NAIK_FULL)
     x_e, x_o, st, info = H.solve_full(links, m, dev(b_e), dev(b_o), mode=md, naik=nk)
     say(mode, info["iters"])
     assert st == H.HISQ_OK
