@@ -323,3 +323,46 @@ def test_config2_32x8_fp64_vs_mixed_bundles():
         rmx = oracle.residual(L, U, N, m, b, host(xmx))
         assert r64.max() <= 1e-10 and rmx.max() <= 1e-10
         _check_solution(L, U, N, m, b, host(xmx), host(x64))
+
+
+def test_concurrent_solves_from_two_threads():
+    """Two host threads, each with its own stream, workspace and problem, solve
+    at the same time (per-thread capture streams and host state, a shared
+    autotune cache); each result equals the same solve run alone, bit for bit."""
+    H = gpu_lib()
+    import threading
+    import torch
+    cases = [((8, 8, 8, 4), 0.05, 4, 301), ((6, 6, 6, 4), 0.02, 3, 302)]
+    inputs = []
+    for L, m, n, seed in cases:
+        U, N = W.make_links(L, 0.3, seed)
+        links = H.Links(L, dev(U), dev(N))
+        b = dev(W.make_sources(L, n, seed + 10))
+        inputs.append((L, m, n, links, b, U, N))
+    ref = [host(H.solve(links, m, b, mode=H.MODE_MIXED, naik=H.NAIK_R14)[0])
+           for L, m, n, links, b, U, N in inputs]
+    torch.cuda.synchronize()
+    got, errors = [None, None], []
+
+    def run(j):
+        try:
+            L, m, n, links, b, U, N = inputs[j]
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    x, st, info = H.solve(links, m, b, mode=H.MODE_MIXED, naik=H.NAIK_R14,
+                                          stream=s.cuda_stream)
+                    assert st == H.HISQ_OK
+                s.synchronize()
+                got[j] = host(x)
+        except Exception as e:  # reported in the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=run, args=(j,)) for j in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not errors, errors
+    for j in range(2):
+        assert got[j] is not None and np.array_equal(got[j], ref[j]), j
