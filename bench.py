@@ -57,12 +57,12 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--tile", default="4,3,4",
+    ap.add_argument("--tile", default=DEFAULT_TILE,
                     help="tile of the solve's D_oe Dslash (and p-update): "
                          "'rhs_per_thread,tile_order,stage_rows' (the autotuner's pick for this "
                          "workload, pinned so that every run and every counter profile times the "
                          "same kernels) or 'auto' (autotune both Dslash kernels)")
-    ap.add_argument("--tile-eo", default="2,256,3,0",
+    ap.add_argument("--tile-eo", default=DEFAULT_TILE_EO,
                     help="tile of the D_eo Dslash with the CG epilogue: "
                          "'rhs_per_thread,block_size,tile_order,stage_rows' (the autotuner's pick), "
                          "used unless --tile is 'auto'")
@@ -74,6 +74,13 @@ def parse():
 
 # Files whose contents decide the Dslash kernels' code: a counter summary taken
 # from other contents no longer describes the kernel.
+# The autotuner's picks for the solve's two Dslash kernels at 48^3 x 12, n = 8,
+# mixed r14 (D_oe: rhs per thread, tile order, staged rows; D_eo with the CG
+# epilogue: rhs per thread, block size, tile order, staged rows), pinned so
+# that every run and every counter profile times the same kernels.
+DEFAULT_TILE = "4,3,4"
+DEFAULT_TILE_EO = "2,256,3,0"
+
 KERNEL_SOURCES = ("paper_1411_4439_amd/csrc/dslash.hip", "paper_1411_4439_amd/csrc/stencil.h",
                   "paper_1411_4439_amd/csrc/naik.h", "paper_1411_4439_amd/csrc/hisq_device.h",
                   "paper_1411_4439_amd/csrc/hisq_internal.h", "paper_1411_4439_amd/build.py")

@@ -213,6 +213,31 @@ def test_headline_mixed_8rhs_true_residual():
         assert res.max() <= 1e-10
 
 
+def test_headline_solve_in_the_benchmark_launch_configuration():
+    """48^3 x 12, n = 8, m = 0.01, mixed r14 with the tiles bench.py pins: the
+    oracle's FP64 true residual of the returned x is <= 1e-10 for every rhs."""
+    H = gpu_lib()
+    import bench
+    L, m, n = (48, 48, 48, 12), 0.01, 8
+    U, N = W.make_links(L, 0.2, W.links_seed(3))
+    links = H.Links(L, dev(U), dev(N))
+    b = W.make_sources(L, n, W.sources_seed(3))
+    nr, order, rows = (int(v) for v in bench.DEFAULT_TILE.split(","))
+    try:
+        H.hisq_set_tuning(1, nr, 64, order, rows)
+        H.hisq_set_tuning_eo(*(int(v) for v in bench.DEFAULT_TILE_EO.split(",")))
+        x, status, info = H.solve(links, m, dev(b), mode=H.MODE_MIXED, naik=H.NAIK_R14)
+    finally:
+        H.hisq_set_tuning(0)
+    say("bench tiles", info["rhs_per_thread"], info["block_size"], info["stage_rows"],
+        info["eo_rhs_per_thread"], info["eo_block_size"], info["iters"])
+    assert status == H.HISQ_OK
+    assert (info["rhs_per_thread"], info["stage_rows"]) == (nr, rows)
+    res = oracle.residual(L, U, N, m, b, host(x))
+    say("oracle true residual", res)
+    assert res.max() <= 1e-10
+
+
 def test_lds_staged_solve_matches_unstaged():
     """A mixed-precision solve forced onto LDS-staged Dslash tiles reports the
     staged shape and returns the same bits as the unstaged tiles (the staged
