@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=8)
     ap.add_argument("--mass", type=float, default=0.01)
     ap.add_argument("--eps", type=float, default=0.2)
-    ap.add_argument("--naik", choices=["r14", "full"], default="r14")
+    ap.add_argument("--naik", choices=["r14", "r13", "r9", "full"], default="r14")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -128,7 +128,7 @@ def main():
 
     L = tuple(int(v) for v in args.lattice.split(","))
     n, m = args.nrhs, args.mass
-    naik = H.NAIK_R14 if args.naik == "r14" else H.NAIK_FULL
+    naik = {"r14": H.NAIK_R14, "r13": H.NAIK_R13, "r9": H.NAIK_R9}.get(args.naik, H.NAIK_FULL)
     Vh = W.half_volume(L)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -137,7 +137,8 @@ def main():
     b = W.make_sources(L, n, W.sources_seed(3))
     log("generated links and sources in %.1f s" % (time.time() - t0))
     Ud, Nd, bd = dev(U), dev(N), dev(b)
-    links = H.Links(L, Ud, Nd, r13=not args.no_sweep, r9=not args.no_sweep)
+    links = H.Links(L, Ud, Nd, r13=not args.no_sweep or args.naik == "r13",
+                    r9=not args.no_sweep or args.naik == "r9")
     torch.cuda.synchronize()
     nr = order = rows = 0
     if args.tile != "auto":
@@ -181,7 +182,7 @@ def main():
         graph_s.append(time.perf_counter() - tg)
 
     # kernel-level figures from the HIP events recorded inside the timed steps
-    nk = "r14" if naik == H.NAIK_R14 else "full"
+    nk = args.naik
     link_b = R.LINK_BYTES_F32[nk]
     vec_b = R.VEC_BYTES_F32
     bytes_oe = Vh * (link_b + 2 * vec_b * n)          # links, read p, write t
