@@ -67,7 +67,7 @@ extern "C" {
 #define HISQ_EINVAL (-1)      /* null pointer, n outside 1..8, tol <= 0, bad enum   */
 #define HISQ_EGEOM (-2)       /* an extent odd or < 4, or the lattice too large     */
 #define HISQ_EWORKSPACE (-3)  /* workspace smaller than hisq_workspace_bytes()      */
-#define HISQ_EPACK (-4)       /* r14/r13 round-trip error above 1e-6 |N| (not s*U(3)) */
+#define HISQ_EPACK (-4)       /* r14/r13 fit error above 1e-10 |N| (not s*U(3))      */
 #define HISQ_EHIP (-5)        /* a HIP runtime call failed                           */
 #define HISQ_NOT_CONVERGED 1  /* maxiter reached before the true residual passed    */
 #define HISQ_BREAKDOWN 2      /* <p, A p> <= 0 or not finite                         */
@@ -112,7 +112,8 @@ enum hisq_kclass {
     HISQ_K_DSLASH_OE = 1, /* t = D_oe p, |t|^2                               */
     HISQ_K_DSLASH_EO = 2, /* D_eo t + CG epilogue: x, r updates, |r|^2       */
     HISQ_K_RELIABLE = 3,  /* FP64 true residual (two FP64 half-Dslash + BLAS) */
-    HISQ_K_COUNT = 4
+    HISQ_K_FORCE = 4,     /* hisq_cg_solve_backward: the link-force kernel    */
+    HISQ_K_COUNT = 5
 };
 
 typedef struct {
@@ -181,10 +182,20 @@ size_t hisq_trace_workspace_bytes(const hisq_geom* g, int nrhs, int mode);
  * one complex c with row2 = c conj(row0 x row1); for R13 as rows 0, 1 and the
  * phase of c, whose modulus 1/|row0| follows from N = s V, V in U(3); for R9
  * as the 9 reals of H = -i log(N / s) with s = |det N|^(1/3).  These calls then
- * synchronize `stream` and return HISQ_EPACK if any round-trip error exceeds
- * 1e-6 of the link's norm (4e-6 for R9, whose FP32 H rounds at that level), or,
- * for R9, if the scales s of the Naik links differ by more than 1e-6 (N is not
- * a positive multiple of a U(3) matrix, or not one multiple throughout).
+ * synchronize `stream` and return HISQ_EPACK if, for R14 and R13, the FP64 fit
+ * of row 2 from rows 0 and 1 misses by more than 1e-10 of the link's norm (N is
+ * not a positive multiple of a U(3) matrix), or, for R9, if the FP32 decode
+ * misses by more than 4e-6 (the FP32 rounding of H is at that level) or the
+ * scales s of the Naik links differ by more than 1e-6 (not one multiple
+ * throughout).  A buffer that fails is left with an invalid header, which
+ * every other entry point rejects.
+ *
+ * Every entry point that takes packed links checks the buffer's header against
+ * its arguments (lattice, precision, Naik storage; FP64/FULL for links64) and
+ * returns HISQ_EINVAL on a mismatch, before launching anything.  The blocking
+ * solvers read the header back with a 256-byte copy on `stream`; hisq_dslash
+ * and hisq_dslash_dmu use what this process recorded when it packed (or last
+ * read) the buffer, and read it back only for a buffer they have not seen.
  */
 int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int prec, int naik,
                     void* packed, void* stream);

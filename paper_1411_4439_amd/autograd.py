@@ -27,8 +27,10 @@ class HisqSolve(torch.autograd.Function):
     def forward(ctx, U, N, m, b, L, mode=H.MODE_FP64, naik=H.NAIK_FULL, tol=1e-10):
         L = tuple(int(v) for v in L)
         mass = float(m)
-        links = H.Links(L, U, N, f32=(mode == H.MODE_MIXED and naik == H.NAIK_FULL),
-                        r14=(mode == H.MODE_MIXED and naik == H.NAIK_R14))
+        mixed = mode == H.MODE_MIXED
+        links = H.Links(L, U, N, f32=(mixed and naik == H.NAIK_FULL),
+                        r14=(mixed and naik == H.NAIK_R14), r13=(mixed and naik == H.NAIK_R13),
+                        r9=(mixed and naik == H.NAIK_R9))
         x, status, info = H.solve(links, mass, b, mode=mode, naik=naik, tol=tol)
         if status != H.HISQ_OK:
             raise RuntimeError("forward solve did not converge: %s" % (info,))

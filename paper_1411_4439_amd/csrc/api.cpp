@@ -89,6 +89,84 @@ const float* naik_scale_of(const void* packed)
     return packed ? &reinterpret_cast<const LinkHeader*>(packed)->naik_scale : nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// Packed-link headers.  A buffer is only valid for the lattice, precision and
+// Naik storage it was packed for: a Dslash that took an r14 block for a full
+// one, or links of a smaller lattice, would read past the allocation.  Every
+// entry point compares the header with its arguments before launching.
+// hisq_pack_links records what it wrote; a buffer the library has not seen in
+// this process (or, for the blocking solvers, any buffer) has its 256-byte
+// header read back once with a device-to-host copy on the caller's stream.
+struct LinkKey {
+    int32_t L[4];
+    int32_t prec;
+    int32_t naik;
+};
+std::mutex g_links_mu;
+std::map<const void*, LinkKey> g_links;
+
+void remember_links(const void* packed, const Lat& lat, int prec, int naik)
+{
+    LinkKey k{{lat.L[0], lat.L[1], lat.L[2], lat.L[3]}, prec, naik};
+    std::lock_guard<std::mutex> lk(g_links_mu);
+    g_links[packed] = k;
+}
+
+void forget_links(const void* packed)
+{
+    std::lock_guard<std::mutex> lk(g_links_mu);
+    g_links.erase(packed);
+}
+
+// HISQ_OK if `packed` holds links packed for (lat, prec, naik); re_read: read
+// the header from the device even if this process packed the buffer.
+int check_links(const char* what, const void* packed, const Lat& lat, int prec, int naik,
+                hipStream_t s, bool re_read)
+{
+    LinkKey k{};
+    bool known = false;
+    if (!re_read) {
+        std::lock_guard<std::mutex> lk(g_links_mu);
+        auto it = g_links.find(packed);
+        if (it != g_links.end()) {
+            k = it->second;
+            known = true;
+        }
+    }
+    if (!known) {
+        LinkHeader h{};
+        HIP_TRY(hipMemcpyAsync(&h, packed, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h.magic != kLinkMagic)
+            return fail(HISQ_EINVAL, "%s: not a packed link buffer (bad header)", what);
+        for (int mu = 0; mu < 4; ++mu) k.L[mu] = h.L[mu];
+        k.prec = h.prec;
+        k.naik = h.naik;
+        std::lock_guard<std::mutex> lk(g_links_mu);
+        g_links[packed] = k;
+    }
+    for (int mu = 0; mu < 4; ++mu)
+        if (k.L[mu] != lat.L[mu])
+            return fail(HISQ_EINVAL, "%s: packed for lattice %dx%dx%dx%d, called with %dx%dx%dx%d",
+                        what, k.L[0], k.L[1], k.L[2], k.L[3], lat.L[0], lat.L[1], lat.L[2],
+                        lat.L[3]);
+    if (k.prec != prec || k.naik != naik)
+        return fail(HISQ_EINVAL, "%s: packed with prec %d, naik %d; called with prec %d, naik %d",
+                    what, k.prec, k.naik, prec, naik);
+    return HISQ_OK;
+}
+
+// The two link buffers of a solve: FP64/FULL, and in MIXED mode FP32 with the
+// params' Naik storage.
+int check_solve_links(const void* links64, const void* links32, const Lat& lat, int mode,
+                      int naik, hipStream_t s)
+{
+    int rc = check_links("links64", links64, lat, HISQ_PREC_F64, HISQ_NAIK_FULL, s, true);
+    if (rc == HISQ_OK && mode == HISQ_MODE_MIXED)
+        rc = check_links("links32", links32, lat, HISQ_PREC_F32, naik, s, true);
+    return rc;
+}
+
 bool valid_nr(int n, int nr)
 {
     if (nr < 1 || nr > n || n % nr != 0) return false;
@@ -425,6 +503,7 @@ struct Prob {
     Ws w;
     Tile t64{}, t32{};    // D_oe with |t|^2 (tuned), the p-update, the FP64 residual
     Tile t64e{}, t32e{};  // D_eo with the CG epilogue (tuned on its own)
+    int bnr = 0;          // rhs per thread in the batched kernels (tuned with the batch)
     CgState* hs = nullptr;  // pinned host copy
     double bb[kMaxRhs] = {};
     bool fin[kMaxRhs] = {};
@@ -443,9 +522,10 @@ struct Engine {
     CgState* states = nullptr;  // device, contiguous, one per problem
     void* table = nullptr;      // device BatchTable (several problems)
     int batch_bs = 128, batch_blocks = 0;
+    CgState* host_buf = nullptr;  // host copy of the states (NULL: the thread's pinned buffer)
     std::vector<hipEvent_t> ev;
-    double kms[HISQ_K_COUNT] = {0, 0, 0, 0};
-    int klaunch[HISQ_K_COUNT] = {0, 0, 0, 0};
+    double kms[HISQ_K_COUNT] = {};
+    int klaunch[HISQ_K_COUNT] = {};
     int updates = 0, polls = 0;
 
     DslashArgs<double> args64(const Prob& q, int parity) const
@@ -584,33 +664,46 @@ struct Engine {
         return HISQ_OK;
     }
 
+    // Batch table over the problems `which` (all if empty), each with its own
+    // rhs tile bnr, for work-groups of bs threads; uploads it and sets
+    // batch_blocks.
     template <typename T>
-    int upload_table(void* host_buf)
+    int upload_table(void* host_buf, const std::vector<int>& which, int bs)
     {
         BatchTable<T>* tab = reinterpret_cast<BatchTable<T>*>(host_buf);
         std::memset(tab, 0, sizeof(*tab));
         int start = 0;
-        for (size_t j = 0; j < P.size(); ++j) {
-            const Prob& q = P[j];
-            BatchProb<T>& bp = tab->p[j];
+        const int np = which.empty() ? (int)P.size() : (int)which.size();
+        for (int jj = 0; jj < np; ++jj) {
+            const Prob& q = P[which.empty() ? jj : which[jj]];
+            BatchProb<T>& bp = tab->p[jj];
             iter_args<T>(q, bp.k1, bp.k2, bp.k3);
-            const Tile& tile = std::is_same<T, float>::value ? q.t32 : q.t64;
             bp.n = q.n;
-            bp.nr = batched_nr_ok(q.n, tile.nr) ? tile.nr : q.n;
+            bp.nr = batched_nr_ok(q.n, q.bnr) ? q.bnr : q.n;
             bp.k1.remap = bp.k2.remap = bp.k3.remap = 0;
             const long threads = (long)q.lat.Vh * (q.n / bp.nr);
-            bp.nblocks = (int)((threads + batch_bs - 1) / batch_bs);
+            bp.nblocks = (int)((threads + bs - 1) / bs);
             bp.k1.ntiles = bp.k2.ntiles = bp.k3.ntiles = bp.nblocks;
             bp.block_start = start;
             start += bp.nblocks;
         }
-        tab->nprob = (int)P.size();
+        tab->nprob = np;
         tab->total_blocks = start;
         batch_blocks = start;
+        batch_bs = bs;
         HIP_TRY(hipMemcpyAsync(table, tab, sizeof(BatchTable<T>), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         return HISQ_OK;
     }
+
+    // The batched autotuner: the rhs tile of every problem and the work-group
+    // size of the batched launches, timed on the problems' own buffers with the
+    // CG state frozen (every rhs active, alpha = 0: x and r keep their values;
+    // setup() initialises everything afterwards).  Each problem's tile is timed
+    // in a batch of its own, then the block size for the whole batch.  The
+    // timed unit is one D_oe (|t|^2) plus one D_eo (CG epilogue) launch.
+    template <typename T>
+    int tune_batched(void* host_buf);
 
     int read_states(CgState* host)
     {
@@ -649,11 +742,119 @@ struct Engine {
         return HISQ_OK;
     }
 
+    int batched_time(void* host_buf, const std::vector<int>& which, int bs, float* ms);
     int setup(CgState* host);
     int poll_and_update(CgState* host);
     int finish(CgState* host, hisq_info* infos, double seconds);
     int run(hisq_info* infos);
 };
+
+// Mean time of one D_oe + one D_eo batched launch over the problems `which`
+// (states armed and frozen by the caller), work-groups of bs threads.
+int Engine::batched_time(void* host_buf, const std::vector<int>& which, int bs, float* ms)
+{
+    int rc = mixed ? upload_table<float>(host_buf, which, bs) : upload_table<double>(host_buf, which, bs);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto pair = [&]() -> int {
+        if (mixed) {
+            const auto* tab = reinterpret_cast<const BatchTable<float>*>(table);
+            HIP_TRY(launch_dslash_batched_f32(EPI_NORM, nk, tab, batch_blocks, bs, s));
+            HIP_TRY(launch_dslash_batched_f32(EPI_CG, nk, tab, batch_blocks, bs, s));
+        } else {
+            const auto* tab = reinterpret_cast<const BatchTable<double>*>(table);
+            HIP_TRY(launch_dslash_batched_f64(EPI_NORM, tab, batch_blocks, bs, s));
+            HIP_TRY(launch_dslash_batched_f64(EPI_CG, tab, batch_blocks, bs, s));
+        }
+        return HISQ_OK;
+    };
+    constexpr int kReps = 3;
+    if ((rc = pair())) return rc;
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < kReps; ++r)
+        if ((rc = pair())) return rc;
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms = t / kReps;
+    return HISQ_OK;
+}
+
+std::map<std::string, std::pair<std::vector<int>, int>> g_batch_cache;  // key -> (tiles, block)
+
+template <typename T>
+int Engine::tune_batched(void* host_buf)
+{
+    std::string key = std::string("B/p") + (mixed ? "1" : "0") + "/k" + std::to_string(nk);
+    for (const Prob& q : P) {
+        char buf[64];
+        snprintf(buf, sizeof(buf), "/%dx%dx%dx%d:%d", q.lat.L[0], q.lat.L[1], q.lat.L[2], q.lat.L[3],
+                 q.n);
+        key += buf;
+    }
+    int mode;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        mode = g_tune_mode;
+        auto it = g_batch_cache.find(key);
+        if (mode == 0 && it != g_batch_cache.end()) {
+            for (size_t j = 0; j < P.size(); ++j) P[j].bnr = it->second.first[j];
+            batch_bs = it->second.second;
+            return HISQ_OK;
+        }
+    }
+    if (mode != 0) {
+        // fixed tiles (tuning modes 1 and 2): every rhs of a site in one thread
+        for (Prob& q : P) q.bnr = q.n;
+        batch_bs = 128;
+        return HISQ_OK;
+    }
+    int rc;
+    for (Prob& q : P) {
+        HIP_TRY(launch_zero(q.w.cnt, q.w.cnt_bytes, s));
+        HIP_TRY(launch_state_reset(q.w.st, q.n, 1, s));
+    }
+    const int sizes[3] = {64, 128, 256};
+    for (size_t j = 0; j < P.size(); ++j) {
+        Prob& q = P[j];
+        int best_nr = q.n;
+        float best = 1e30f;
+        for (int nr : {q.n, q.n / 2}) {
+            if (nr < 1 || !batched_nr_ok(q.n, nr)) continue;
+            q.bnr = nr;
+            for (int bs : sizes) {
+                float ms;
+                if ((rc = batched_time(host_buf, {(int)j}, bs, &ms))) return rc;
+                if (ms < best) {
+                    best = ms;
+                    best_nr = nr;
+                }
+            }
+        }
+        q.bnr = best_nr;
+    }
+    float best = 1e30f;
+    int best_bs = 128;
+    for (int bs : sizes) {
+        float ms;
+        if ((rc = batched_time(host_buf, {}, bs, &ms))) return rc;
+        if (ms < best) {
+            best = ms;
+            best_bs = bs;
+        }
+    }
+    batch_bs = best_bs;
+    std::vector<int> tiles;
+    for (const Prob& q : P) tiles.push_back(q.bnr);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_batch_cache[key] = {tiles, batch_bs};
+    return HISQ_OK;
+}
 
 int Engine::setup(CgState* host)
 {
@@ -837,11 +1038,11 @@ int Engine::finish(CgState* host, hisq_info* infos, double seconds)
             const Tile& t = mixed ? q.t32 : q.t64;
             const Tile& te = mixed ? q.t32e : q.t64e;
             info->block_size = P.size() == 1 ? t.bs : batch_bs;
-            info->rhs_per_thread = t.nr;
+            info->rhs_per_thread = P.size() == 1 ? t.nr : q.bnr;
             info->tile_order = P.size() == 1 ? t.remap : 0;
             info->stage_rows = P.size() == 1 ? t.rows : 0;
             info->eo_block_size = P.size() == 1 ? te.bs : batch_bs;
-            info->eo_rhs_per_thread = te.nr;
+            info->eo_rhs_per_thread = P.size() == 1 ? te.nr : q.bnr;
             info->eo_tile_order = P.size() == 1 ? te.remap : 0;
             info->eo_stage_rows = P.size() == 1 ? te.rows : 0;
         }
@@ -880,8 +1081,8 @@ int Engine::run(hisq_info* infos)
 {
     const auto t_start = std::chrono::steady_clock::now();
     int rc;
-    CgState* host = nullptr;
-    if ((rc = host_state(&host))) return rc;
+    CgState* host = host_buf;
+    if (!host && (rc = host_state(&host))) return rc;
 
     // tiles (autotuned per problem on the reducing D_oe kernel; the state and
     // counters are armed for it here and reset again by setup())
@@ -892,7 +1093,7 @@ int Engine::run(hisq_info* infos)
         probe.in = q.x;
         probe.out = q.w.t64;
         if ((rc = get_tile(q.lat, q.n, HISQ_PREC_F64, HISQ_NAIK_FULL, probe, s, &q.t64, EPI_NORM))) return rc;
-        if (mixed) {
+        if (mixed && P.size() == 1) {
             DslashArgs<float> p32{};
             p32.lat = q.lat;
             p32.parity = 1;
@@ -928,17 +1129,17 @@ int Engine::run(hisq_info* infos)
             }
         }
     }
-    if ((rc = setup(host))) return rc;
     if (P.size() > 1) {
-        // one work-group size for the batched launch: the largest problem's
-        size_t big = 0;
-        for (size_t j = 1; j < P.size(); ++j)
-            if (P[j].lat.Vh * P[j].n > P[big].lat.Vh * P[big].n) big = j;
-        batch_bs = unstaged(mixed ? P[big].t32 : P[big].t64).bs;
         static thread_local std::vector<char> tabbuf;
         tabbuf.resize(std::max(sizeof(BatchTable<double>), sizeof(BatchTable<float>)));
-        rc = mixed ? upload_table<float>(tabbuf.data()) : upload_table<double>(tabbuf.data());
+        rc = mixed ? tune_batched<float>(tabbuf.data()) : tune_batched<double>(tabbuf.data());
         if (rc) return rc;
+        if ((rc = setup(host))) return rc;
+        rc = mixed ? upload_table<float>(tabbuf.data(), {}, batch_bs)
+                   : upload_table<double>(tabbuf.data(), {}, batch_bs);
+        if (rc) return rc;
+    } else if ((rc = setup(host))) {
+        return rc;
     }
 
     const int kblk = poll_block_size();
@@ -1005,9 +1206,10 @@ int check_params(const hisq_params* p, int n)
 
 int solve_impl(double mass, int nrhs, const hisq_params* p, const void* links64,
                const void* links32, const double* b_e, double* x_e, const Ws& w, hisq_info* info,
-               void* stream, const Lat& lat)
+               void* stream, const Lat& lat, CgState* host_buf = nullptr)
 {
     Engine E;
+    E.host_buf = host_buf;
     E.prm = *p;
     E.mixed = p->mode == HISQ_MODE_MIXED;
     E.nk = E.mixed ? p->naik : HISQ_NAIK_FULL;
@@ -1170,6 +1372,49 @@ int check_problems(int nprob, const hisq_problem* probs, int mode)
 
 }  // namespace
 
+// The body of hisq_cg_solve: argument and link checks, then the solve over the
+// workspace `ws`; host_buf (nullable) receives the host copies of the CG state
+// instead of the calling thread's pinned buffer.
+int hisq::cg_solve_on(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                      const void* links64, const void* links32, const double* b_e, double* x_e,
+                      void* ws, size_t ws_bytes, hisq_info* info, void* stream, CgState* host_buf)
+{
+    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
+    Lat lat;
+    int rc = check_geom(g, &lat);
+    if (rc) return rc;
+    if ((rc = check_params(p, nrhs))) return rc;
+    if (!links64 || !b_e || !x_e || !ws) return fail(HISQ_EINVAL, "NULL pointer");
+    HISQ_CHECK_ALIGNED(links64, links32, b_e, x_e, ws);
+    if (p->mode == HISQ_MODE_MIXED && !links32)
+        return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
+    if (!std::isfinite(mass)) return fail(HISQ_EINVAL, "mass must be finite");
+    Ws w;
+    const size_t need = ws_layout(lat, nrhs, p->mode, WS_SOLVE, nullptr, &w);
+    if (ws_bytes < need)
+        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if ((rc = check_solve_links(links64, links32, lat, p->mode, p->naik,
+                                reinterpret_cast<hipStream_t>(stream))))
+        return rc;
+    ws_layout(lat, nrhs, p->mode, WS_SOLVE, reinterpret_cast<char*>(ws), &w);
+    return solve_impl(mass, nrhs, p, links64, links32, b_e, x_e, w, info, stream, lat, host_buf);
+}
+
+int hisq::report_error(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+size_t hisq::cg_workspace_bytes(const Lat& lat, int nrhs, int mode)
+{
+    Ws w;
+    return ws_layout(lat, nrhs, mode, WS_SOLVE, nullptr, &w);
+}
+
 // ===========================================================================
 // C ABI
 extern "C" {
@@ -1255,9 +1500,18 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
     if (naik != HISQ_NAIK_FULL && prec != HISQ_PREC_F32)
         return fail(HISQ_EINVAL, "compressed Naik storage is FP32 only");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    forget_links(packed);
     HIP_TRY(launch_pack(lat, reinterpret_cast<const d2*>(U), reinterpret_cast<const d2*>(N), prec,
                         naik, packed, s));
     if (naik != HISQ_NAIK_FULL) {
+        // a buffer that fails its round-trip check is left without a valid
+        // header, so that no later call accepts it
+        auto reject = [&]() -> int {
+            const uint32_t zero = 0;
+            HIP_TRY(hipMemcpyAsync(packed, &zero, sizeof(zero), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            return HISQ_OK;
+        };
         LinkHeader h{};
         HIP_TRY(hipMemcpyAsync(&h, packed, sizeof(h), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -1267,17 +1521,22 @@ int hisq_pack_links(const hisq_geom* g, const double* U, const double* N, int pr
         std::memcpy(&smax, &h.scale_max_bits, sizeof(smax));
         const char* name = naik == HISQ_NAIK_R14 ? "r14" : naik == HISQ_NAIK_R13 ? "r13" : "r9";
         const float tol = naik == HISQ_NAIK_R9 ? kR9Tolerance : kNaikTolerance;
-        if (!(err <= tol))
+        if (!(err <= tol)) {
+            if ((rc = reject())) return rc;
             return fail(HISQ_EPACK, "%s round-trip error %g: Naik links are not s * U(3)", name, err);
+        }
         if (naik == HISQ_NAIK_R9) {
-            if (!(smin > 0.0f) || !(smax - smin <= kR9ScaleSpread * smax))
+            if (!(smin > 0.0f) || !(smax - smin <= kR9ScaleSpread * smax)) {
+                if ((rc = reject())) return rc;
                 return fail(HISQ_EPACK, "r9 needs one Naik scale: |det N|^(1/3) spans %g .. %g", smin, smax);
+            }
             const float scale = 0.5f * (smin + smax);
             LinkHeader* hd = reinterpret_cast<LinkHeader*>(packed);
             HIP_TRY(hipMemcpyAsync(&hd->naik_scale, &scale, sizeof(scale), hipMemcpyHostToDevice, s));
             HIP_TRY(hipStreamSynchronize(s));
         }
     }
+    remember_links(packed, lat, prec, naik);
     return HISQ_OK;
 }
 
@@ -1300,6 +1559,7 @@ int hisq_dslash(const hisq_geom* g, int out_parity, int nrhs, int prec, int naik
     if (layout != HISQ_LAYOUT_SITE && layout != HISQ_LAYOUT_COLOUR)
         return fail(HISQ_EINVAL, "bad layout %d", layout);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_links("packed", packed, lat, prec, naik, s, false))) return rc;
     const int nk = naik;
     const bool cm = layout == HISQ_LAYOUT_COLOUR;
     Tile t;
@@ -1330,22 +1590,8 @@ int hisq_cg_solve(const hisq_geom* g, double mass, int nrhs, const hisq_params* 
                   const void* links64, const void* links32, const double* b_e, double* x_e,
                   void* ws, size_t ws_bytes, hisq_info* info, void* stream)
 {
-    (void)hipGetLastError();  // drop a stale error left by an earlier failed call
-    Lat lat;
-    int rc = check_geom(g, &lat);
-    if (rc) return rc;
-    if ((rc = check_params(p, nrhs))) return rc;
-    if (!links64 || !b_e || !x_e || !ws) return fail(HISQ_EINVAL, "NULL pointer");
-    HISQ_CHECK_ALIGNED(links64, links32, b_e, x_e, ws);
-    if (p->mode == HISQ_MODE_MIXED && !links32)
-        return fail(HISQ_EINVAL, "MIXED mode needs FP32 links");
-    if (!std::isfinite(mass)) return fail(HISQ_EINVAL, "mass must be finite");
-    Ws w;
-    const size_t need = ws_layout(lat, nrhs, p->mode, WS_SOLVE, nullptr, &w);
-    if (ws_bytes < need)
-        return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
-    ws_layout(lat, nrhs, p->mode, WS_SOLVE, reinterpret_cast<char*>(ws), &w);
-    return solve_impl(mass, nrhs, p, links64, links32, b_e, x_e, w, info, stream, lat);
+    return hisq::cg_solve_on(g, mass, nrhs, p, links64, links32, b_e, x_e, ws, ws_bytes, info,
+                             stream, nullptr);
 }
 
 int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
@@ -1368,8 +1614,9 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     const size_t need = ws_layout(lat, nrhs, p->mode, WS_BACKWARD, nullptr, &w);
     if (ws_bytes < need)
         return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
-    ws_layout(lat, nrhs, p->mode, WS_BACKWARD, reinterpret_cast<char*>(ws), &w);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_solve_links(links64, links32, lat, p->mode, p->naik, s))) return rc;
+    ws_layout(lat, nrhs, p->mode, WS_BACKWARD, reinterpret_cast<char*>(ws), &w);
     d2* y = grad_b ? reinterpret_cast<d2*>(grad_b) : w.y;
     // adjoint solve: A is Hermitian, so A y = grad_x uses the same operator
     hisq_params q = *p;
@@ -1389,11 +1636,28 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     a.in = y;
     a.out = w.sy;
     HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, false));
+    hipEvent_t fe[2] = {nullptr, nullptr};
+    if (p->profile) {
+        HIP_TRY(hipEventCreate(&fe[0]));
+        HIP_TRY(hipEventCreate(&fe[1]));
+        HIP_TRY(hipEventRecord(fe[0], s));
+    }
     HIP_TRY(launch_force(lat, nrhs, reinterpret_cast<const d2*>(x_e), y, w.tx, w.sy,
                          reinterpret_cast<d2*>(grad_U), reinterpret_cast<d2*>(grad_N), s));
+    if (p->profile) HIP_TRY(hipEventRecord(fe[1], s));
     HIP_TRY(launch_redot(y, reinterpret_cast<const d2*>(x_e), lat.Vh, nrhs, -8.0 * mass, grad_m,
                          w.red, w.cnt, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (p->profile) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, fe[0], fe[1]));
+        hipEventDestroy(fe[0]);
+        hipEventDestroy(fe[1]);
+        if (info) {
+            info->kernel_ms[HISQ_K_FORCE] = ms;
+            info->kernel_launches[HISQ_K_FORCE] = 1;
+        }
+    }
     return st;
 }
 
@@ -1411,6 +1675,8 @@ int hisq_dslash_dmu(const hisq_geom* g, int out_parity, int nrhs, int nder, cons
     if (nder < 0 || nder > HISQ_MAX_DERIVATIVE)
         return fail(HISQ_EINVAL, "nder = %d outside 0..%d", nder, HISQ_MAX_DERIVATIVE);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if ((rc = check_links("links64", links64, lat, HISQ_PREC_F64, HISQ_NAIK_FULL, s, false)))
+        return rc;
     const d2* vin = reinterpret_cast<const d2*>(in);
     d2* vout = reinterpret_cast<d2*>(out);
     const d2* lk = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, out_parity);
@@ -1458,6 +1724,9 @@ int hisq_solve_full(const hisq_geom* g, double mass, int nrhs, const hisq_params
     const size_t need = ws_layout(lat, nrhs, p->mode, WS_FULL, nullptr, &w);
     if (ws_bytes < need)
         return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if ((rc = check_solve_links(links64, links32, lat, p->mode, p->naik,
+                                reinterpret_cast<hipStream_t>(stream))))
+        return rc;
     ws_layout(lat, nrhs, p->mode, WS_FULL, reinterpret_cast<char*>(ws), &w);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     rc = full_impl(mass, nrhs, p, links64, links32, reinterpret_cast<const d2*>(b_e),
@@ -1489,6 +1758,9 @@ int hisq_trace_estimate(const hisq_geom* g, double mass, int nrhs, const hisq_pa
     const size_t need = ws_layout(lat, nrhs, p->mode, WS_TRACE, nullptr, &w);
     if (ws_bytes < need)
         return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    if ((rc = check_solve_links(links64, links32, lat, p->mode, p->naik,
+                                reinterpret_cast<hipStream_t>(stream))))
+        return rc;
     ws_layout(lat, nrhs, p->mode, WS_TRACE, reinterpret_cast<char*>(ws), &w);
     return trace_impl(mass, nrhs, p, links64, links32, ninsert, orders,
                       reinterpret_cast<const d2*>(eta_e), reinterpret_cast<const d2*>(eta_o), est, w,
@@ -1521,6 +1793,12 @@ int hisq_cg_solve_batched(int nprob, const hisq_problem* probs, const hisq_param
     const size_t need = batched_layout(nprob, probs, p->mode, nullptr, &w, &states, &table);
     if (ws_bytes < need)
         return fail(HISQ_EWORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, need);
+    for (int j = 0; j < nprob; ++j) {
+        const Lat lat = make_lat(probs[j].geom);
+        if ((rc = check_solve_links(probs[j].links64, probs[j].links32, lat, p->mode, p->naik,
+                                    reinterpret_cast<hipStream_t>(stream))))
+            return fail(rc, "problem %d: %s", j, std::string(g_err).c_str());
+    }
     batched_layout(nprob, probs, p->mode, reinterpret_cast<char*>(ws), &w, &states, &table);
     Engine E;
     E.prm = *p;

@@ -36,6 +36,7 @@ __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int off = base + Lay::colour(c, a.lat.Vh);
+            // converged (masked) rhs are not written
             C rv[NR], pv[NR];
             load_rhs<NR>(a.r + off, rv);
             load_rhs<NR>(a.p + off, pv);
@@ -43,12 +44,11 @@ __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, 
             for (int k = 0; k < NR; ++k) {
                 // beta = 0 starts (or restarts) the recursion: p = r exactly, even
                 // if p held non-finite values
-                if (act[k])
-                    pv[k] = beta[k] == T(0) ? rv[k]
-                                            : C{rv[k].x + beta[k] * pv[k].x, rv[k].y + beta[k] * pv[k].y};
-                part[k] += (double)pv[k].x * pv[k].x + (double)pv[k].y * pv[k].y;
+                pv[k] = beta[k] == T(0) ? rv[k]
+                                        : C{rv[k].x + beta[k] * pv[k].x, rv[k].y + beta[k] * pv[k].y};
+                if (act[k]) part[k] += (double)pv[k].x * pv[k].x + (double)pv[k].y * pv[k].y;
             }
-            store_rhs<NR>(a.p + off, pv);
+            store_rhs_on<NR>(a.p + off, pv, act);
         }
     }
     double total;
@@ -126,12 +126,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupdate_flat(const PupdateArgs<T>
             load_rhs<NRT>(a.p + j * NRT, pv);
 #pragma unroll
             for (int k = 0; k < NRT; ++k) {
-                if (act[k])
-                    pv[k] = beta[k] == T(0) ? rv[k]
-                                            : C{rv[k].x + beta[k] * pv[k].x, rv[k].y + beta[k] * pv[k].y};
-                part[k] += (double)pv[k].x * pv[k].x + (double)pv[k].y * pv[k].y;
+                pv[k] = beta[k] == T(0) ? rv[k]
+                                        : C{rv[k].x + beta[k] * pv[k].x, rv[k].y + beta[k] * pv[k].y};
+                if (act[k]) part[k] += (double)pv[k].x * pv[k].x + (double)pv[k].y * pv[k].y;
             }
-            store_rhs<NRT>(a.p + j * NRT, pv);
+            store_rhs_on<NRT>(a.p + j * NRT, pv, act);
         }
     }
     double total;

@@ -141,19 +141,24 @@ __device__ __forceinline__ void dslash_site(const Lat& lat, int P, int i, int g,
 #define HISQ_FP32_LINK_LOOKAHEAD 1
 #endif
     constexpr int LD = sizeof(T) == 4 ? HISQ_FP32_LINK_LOOKAHEAD : 1;
-    C m[LD + 1][9];
+    // lanes sharing a link: the site's lanes, in quads when there are 8
+    constexpr int G = (NRHS / NR) < 4 ? NRHS / NR : 4;
+    const int gl = g % G;
+    LinkRaw<T, G> lr[LD + 1];
     C v[2][3][NR];
-    load_link<T, NK, slot_at(0)>(lk, Vh, i, m[0]);
-    if constexpr (LD == 2) load_link<T, NK, slot_at(1)>(lk, Vh, i, m[1]);
+    load_link_part<T, NK, slot_at(0), G>(lk, Vh, i, gl, lr[0]);
+    if constexpr (LD == 2) load_link_part<T, NK, slot_at(1), G>(lk, Vh, i, gl, lr[1]);
     load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(0)>(lat, sc), g, v[0]);
     static_for<0, 16>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (k + LD < 16)
-            load_link<T, NK, slot_at(k + LD)>(lk, Vh, i, m[(k + LD) % (LD + 1)]);
+            load_link_part<T, NK, slot_at(k + LD), G>(lk, Vh, i, gl, lr[(k + LD) % (LD + 1)]);
         if constexpr (k + 1 < 16)
             load_vec<T, NRHS, NR, CM>(in, Vh, neighbour<slot_at(k + 1)>(lat, sc), g, v[(k + 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
-        apply_slot<T, NR, NK, slot_at(k)>(m[k % (LD + 1)], v[k & 1], acc, ns);
+        C m[9];
+        share_link<T, NK, slot_at(k), G>(lr[k % (LD + 1)], m);
+        apply_slot<T, NR, NK, slot_at(k)>(m, v[k & 1], acc, ns);
         __builtin_amdgcn_sched_barrier(0);
     });
 }
@@ -282,9 +287,13 @@ __device__ __forceinline__ int lds_neighbour(const Lat& lat, int r, int xh, int 
 // The global reads that open the pipeline (slot 0's link, the first two
 // global neighbours): issued before the work-group's staging barrier, so
 // that their latency overlaps the staging reads instead of following them.
+// lanes that share one site's link loads (quads when a site has 8 lanes)
+template <int NRHS, int NR>
+constexpr int link_group() { return (NRHS / NR) < 4 ? NRHS / NR : 4; }
+
 template <typename T, int NRHS, int NR, int NK>
 struct LdsHead {
-    cplx<T> m[9];
+    LinkRaw<T, link_group<NRHS, NR>()> m;
     cplx<T> v0[3][NR], v1[3][NR];
 };
 
@@ -294,7 +303,8 @@ __device__ __forceinline__ void lds_head(const Lat& lat, int P, int i, int g,
                                          const cplx<T>* __restrict__ in, LdsHead<T, NRHS, NR, NK>& h)
 {
     const SiteCoord sc = site_coord(lat, P, i);
-    load_link<T, NK, slot_at(0)>(lk, lat.Vh, i, h.m);
+    constexpr int G = link_group<NRHS, NR>();
+    load_link_part<T, NK, slot_at(0), G>(lk, lat.Vh, i, g % G, h.m);
     load_vec<T, NRHS, NR, true>(in, lat.Vh, neighbour<slot_at(0)>(lat, sc), g, h.v0);
     load_vec<T, NRHS, NR, true>(in, lat.Vh, neighbour<slot_at(2)>(lat, sc), g, h.v1);
 }
@@ -316,11 +326,12 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < NR; ++k) acc[c][k] = C{0, 0};
-    C m[2][9];
+    constexpr int G = link_group<NRHS, NR>();
+    const int gl = g % G;
+    LinkRaw<T, G> m[2];
     C vg[2][3][NR];
     C vl[3][NR];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) m[0][e] = h.m[e];
+    m[0] = h.m;
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
@@ -331,18 +342,22 @@ __device__ __forceinline__ void dslash_site_lds(const Lat& lat, int P, int i, in
     static_for<0, 16>([&](auto K) {
         constexpr int k = decltype(K)::value;
         if constexpr (k % 2 == 0) {
-            load_link<T, NK, slot_at(k + 1)>(lk, Vh, i, m[(k + 1) & 1]);
+            load_link_part<T, NK, slot_at(k + 1), G>(lk, Vh, i, gl, m[(k + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
-            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vg[(k >> 1) & 1], acc, ns);
+            C mk[9];
+            share_link<T, NK, slot_at(k), G>(m[k & 1], mk);
+            apply_slot<T, NR, NK, slot_at(k)>(mk, vg[(k >> 1) & 1], acc, ns);
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (k + 2 < 16) load_link<T, NK, slot_at(k + 2)>(lk, Vh, i, m[k & 1]);
+            if constexpr (k + 2 < 16) load_link_part<T, NK, slot_at(k + 2), G>(lk, Vh, i, gl, m[k & 1]);
             if constexpr (k + 4 < 16)
                 load_vec<T, NRHS, NR, true>(in, Vh, neighbour<slot_at(k + 4)>(lat, sc), g,
                                             vg[(k >> 1) & 1]);
             load_vec_lds<T, NRHS, NR>(lds, cstride,
                                       lds_neighbour<slot_at(k + 1)>(lat, r, xh, sc.x), g, vl);
         } else {
-            apply_slot<T, NR, NK, slot_at(k)>(m[k & 1], vl, acc, ns);
+            C mk[9];
+            share_link<T, NK, slot_at(k), G>(m[k & 1], mk);
+            apply_slot<T, NR, NK, slot_at(k)>(mk, vl, acc, ns);
         }
         __builtin_amdgcn_sched_barrier(0);
     });
@@ -474,6 +489,9 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
             }
         } else if constexpr (EPI == EPI_CG) {
             if (any_act) {
+            // converged (masked) rhs are not written (and not read where the
+            // whole tile of the thread is masked); their partial sums stay
+            // zero and their finisher ignores them
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 C pv[NR], xv[NR], rv[NR];
@@ -483,16 +501,14 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     const C q = C{m4 * pv[k].x - acc[c][k].x, m4 * pv[k].y - acc[c][k].y};
-                    if (act[k]) {
-                        xv[k] = C{xv[k].x + alpha[k] * pv[k].x, xv[k].y + alpha[k] * pv[k].y};
-                        rv[k] = C{rv[k].x - alpha[k] * q.x, rv[k].y - alpha[k] * q.y};
-                    }
-                    part[k] += norm2c<T>(rv[k]);
+                    xv[k] = C{xv[k].x + alpha[k] * pv[k].x, xv[k].y + alpha[k] * pv[k].y};
+                    rv[k] = C{rv[k].x - alpha[k] * q.x, rv[k].y - alpha[k] * q.y};
+                    if (act[k]) part[k] += norm2c<T>(rv[k]);
                 }
                 // plain stores: L2 merges the partial lines of consecutive
                 // store instructions before they reach HBM
-                store_rhs<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
-                store_rhs<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
+                store_rhs_on<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv, act);
+                store_rhs_on<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv, act);
             }
             }
         } else if constexpr (EPI == EPI_RESID) {

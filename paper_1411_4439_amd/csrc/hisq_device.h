@@ -65,6 +65,11 @@ __device__ __forceinline__ uint32_t add_coherent(uint32_t* p, uint32_t v)
 // Wait until this wave's outstanding memory operations have completed, i.e.
 // its coherent stores have been performed, before it signals a counter.
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// The reading side: once a work-group has seen from the counter that it
+// arrived last, an agent-scope acquire keeps its loads of the partials after
+// that observation (the compiler may not hoist them, and the vector L1 is
+// invalidated, so no line cached before the counter update is reused).
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Sum over all 64 lanes by an xor butterfly: every lane ends with the same,
 // bitwise identical total (each step adds the same two values).
@@ -87,6 +92,20 @@ __device__ __forceinline__ double wave_sum(double v)
 // of rhs k in *total.  The grid is the nblk work-groups of one problem, this
 // one being number bid.  red: [nblk][NRHS] partials then [ngroups][NRHS] group
 // sums; cnt: [1 + ngroups] counters, zero on entry and re-armed on exit.
+//
+// Ordering.  A writer stores its partials with agent-scope atomic stores,
+// waits (s_waitcnt vmcnt(0)) until the memory system has acknowledged them --
+// an agent-scope atomic store is acknowledged once it is visible at the
+// device-coherent level, bypassing the XCD's non-coherent L2 -- and only then
+// issues its counter increment.  The last arriving work-group observes the
+// final count through the returned value of its own read-modify-write, then
+// executes an agent-scope acquire before it loads the partials with
+// agent-scope atomic loads.  So every partial was performed at the coherent
+// level before the increment that counted it, and every load of the reader
+// follows its observation of that count.  The writer side uses no release
+// fence: on this chip an agent-scope release writes back the XCD's whole L2,
+// which one work-group per launch can afford but every work-group cannot; the
+// completion wait orders exactly the stores the reader needs.
 template <int NRHS, int NR>
 __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, int nblk, int bid,
                                 double* total)
@@ -125,6 +144,7 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
     if (lane == 0) prev = add_coherent(&cnt[1 + grp], 1u);
     prev = __shfl(prev, 0, 64);
     if (prev != (uint32_t)(gn - 1)) return false;
+    acquire_agent();
 
     // stage 2: the last work-group of the group
     double acc[NRHS];
@@ -143,6 +163,7 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
     if (lane == 0) prev = add_coherent(&cnt[0], 1u);
     prev = __shfl(prev, 0, 64);
     if (prev != (uint32_t)(ngroups - 1)) return false;
+    acquire_agent();
 
     // stage 3: the last group
 #pragma unroll
@@ -240,6 +261,38 @@ __device__ __forceinline__ void store_rhs(d2* __restrict__ p, const d2 (&v)[NR])
 {
 #pragma unroll
     for (int k = 0; k < NR; ++k) st<NT>(p + k, v[k]);
+}
+
+// Masked stores for the CG updates: rhs k is written only if on[k] (converged
+// rhs keep their values untouched in memory); a 16-byte FP32 pair with one rhs
+// on stores that rhs alone.
+template <int NR>
+__device__ __forceinline__ void store_rhs_on(f2* __restrict__ p, const f2 (&v)[NR], const bool (&on)[NR])
+{
+    if constexpr (NR % 2 == 0) {
+        f4* q = reinterpret_cast<f4*>(p);
+#pragma unroll
+        for (int k = 0; k < NR / 2; ++k) {
+            if (on[2 * k] && on[2 * k + 1])
+                q[k] = f4{v[2 * k].x, v[2 * k].y, v[2 * k + 1].x, v[2 * k + 1].y};
+            else if (on[2 * k])
+                p[2 * k] = v[2 * k];
+            else if (on[2 * k + 1])
+                p[2 * k + 1] = v[2 * k + 1];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NR; ++k)
+            if (on[k]) p[k] = v[k];
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void store_rhs_on(d2* __restrict__ p, const d2 (&v)[NR], const bool (&on)[NR])
+{
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (on[k]) p[k] = v[k];
 }
 
 }  // namespace hisq

@@ -55,7 +55,9 @@ constexpr int kMaxBlock = 256;
 // neighbour rows.
 constexpr int kMaxBlockLds = 512;
 constexpr int kMaxStageBytes = 64 * 1024;
-constexpr float kNaikTolerance = 1e-6f;  // r14 / r13 round-trip error bound
+// r14 / r13: bound on the relative error of the FP64 fit row2 = c conj(row0 x row1)
+// (before rounding to FP32); exact fits of s*U(3) links stay near 1e-15
+constexpr float kNaikTolerance = 1e-10f;
 constexpr float kR9Tolerance = 4e-6f;    // r9: bounded by the FP32 rounding of H
 constexpr float kR9ScaleSpread = 1e-6f;  // r9: relative spread of the Naik scales
 
@@ -273,6 +275,16 @@ hipError_t launch_dslash_dmu(const Lat& lat, int parity, int nrhs, int nder, con
 hipError_t launch_zero_sel(d2* v, size_t ncplx, int nrhs, const CgState* st, hipStream_t s);
 hipError_t launch_redot(const d2* y, const d2* x, int Vh, int nrhs, double scale, double* out,
                         double* red, uint32_t* cnt, hipStream_t s);
+
+// The solve of hisq_cg_solve over a workspace region (api.cpp); host_buf, if
+// not NULL, holds HISQ_MAX_PROBLEMS host copies of the CG state in place of
+// the calling thread's pinned buffer.
+int cg_solve_on(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                const void* links64, const void* links32, const double* b_e, double* x_e,
+                void* ws, size_t ws_bytes, hisq_info* info, void* stream, CgState* host_buf);
+size_t cg_workspace_bytes(const Lat& lat, int nrhs, int mode);
+// Sets the message of hisq_last_error() for this thread; returns code.
+int report_error(int code, const char* fmt, ...);
 
 // Link packing (pack.hip) and the link force (force.hip).
 hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int naik,

@@ -86,6 +86,100 @@ __device__ __forceinline__ void load_link(const cplx<T>* __restrict__ lk, int Vh
     }
 }
 
+// A link matrix shared by the G adjacent lanes that compute the rhs tiles of
+// one site (G = 1, 2, 4).  Loading the whole matrix in every lane would move
+// each 16-byte word G times through the vector memory pipeline; instead the
+// slot's nw = nr / 4 words are dealt round-robin to the lanes of the group
+// (word w to lane w mod G), each lane loads only its own, and when the slot is
+// used every lane gathers all words with DPP permutes inside its quad (a VALU
+// operation, no memory traffic).  The nr mod 4 trailing reals are one small
+// load per lane.  FP64 links keep one lane per load (their kernels run G <= 2
+// and use every register for the doubles).
+template <typename T, int G>
+struct LinkRaw {
+    static constexpr int kW = (4 + G - 1) / G;  // words per lane (<= 4 per slot)
+    f4 w[kW];
+    f2 t;
+};
+template <int G>
+struct LinkRaw<double, G> {
+    d2 m[9];
+};
+
+// Value of v held by lane SRC of this lane's group of G (quad permute:
+// G = 4, lanes 4k..4k+3; G = 2, lanes 2k, 2k+1).  Every lane of the group must
+// be active.
+template <int G, int SRC>
+__device__ __forceinline__ float group_bcast(float v)
+{
+    static_assert(G == 2 || G == 4, "groups of 2 or 4 lanes");
+    constexpr int ctrl = G == 4 ? SRC * 0x55 : (SRC | SRC << 2 | (2 + SRC) << 4 | (2 + SRC) << 6);
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xF, 0xF, false));
+}
+
+template <int G, int SRC>
+__device__ __forceinline__ f4 group_bcast4(f4 v)
+{
+    if constexpr (G == 1) {
+        return v;
+    } else {
+        return f4{group_bcast<G, SRC>(v.x), group_bcast<G, SRC>(v.y), group_bcast<G, SRC>(v.z),
+                  group_bcast<G, SRC>(v.w)};
+    }
+}
+
+// Issue this lane's share of the loads of slot S (lane g of its group).
+template <typename T, int NK, int S, int G>
+__device__ __forceinline__ void load_link_part(const cplx<T>* __restrict__ lk, int Vh, int i, int g,
+                                               LinkRaw<T, G>& r)
+{
+    if constexpr (sizeof(T) == 8) {
+        load_link<T, NK, S>(lk, Vh, i, r.m);
+    } else {
+        const T* base = reinterpret_cast<const T*>(lk) + (size_t)slot_real_start(S, NK) * Vh;
+        constexpr int nr = slot_reals(S, NK);
+        constexpr int nw = nr / 4, rem = nr % 4;
+        const f4* wp = reinterpret_cast<const f4*>(base) + i;
+#pragma unroll
+        for (int j = 0; j < LinkRaw<T, G>::kW; ++j) {
+            if (j * G < nw) {
+                // a lane left without a word of this round loads the last one
+                // again (no divergent branch in the pipeline; same cache line)
+                const int w = min((G == 1 ? 0 : g) + j * G, nw - 1);
+                r.w[j] = __builtin_nontemporal_load(wp + (size_t)w * Vh);
+            }
+        }
+        const T* tail = base + (size_t)4 * nw * Vh;
+        if constexpr (rem == 2) {
+            r.t = __builtin_nontemporal_load(reinterpret_cast<const f2*>(tail) + i);
+        } else if constexpr (rem == 1) {
+            r.t = f2{__builtin_nontemporal_load(tail + i), 0.f};
+        }
+    }
+}
+
+// The whole matrix of slot S from the group's shares: m[e] element e (row-major);
+// for compressed Naik slots m[0..5] rows 0 and 1 and m[6] the stored coefficient.
+template <typename T, int NK, int S, int G>
+__device__ __forceinline__ void share_link(const LinkRaw<T, G>& r, cplx<T> (&m)[9])
+{
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) m[e] = r.m[e];
+    } else {
+        constexpr int nr = slot_reals(S, NK);
+        constexpr int nw = nr / 4, rem = nr % 4;
+        static_for<0, nw>([&](auto W) {
+            constexpr int w = decltype(W)::value;
+            const f4 q = group_bcast4<G, w % G>(r.w[w / G]);
+            m[2 * w] = cplx<T>{q.x, q.y};
+            m[2 * w + 1] = cplx<T>{q.z, q.w};
+        });
+        if constexpr (rem > 0) m[2 * nw] = r.t;
+    }
+}
+
 // Site coordinates and the neighbour index of slot S = 4*hop + mu, hop
 // (+1, -1, +3, -3), in the other parity's index space.
 struct SiteCoord {

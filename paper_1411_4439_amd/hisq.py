@@ -30,7 +30,8 @@ PREC_F64, PREC_F32 = 0, 1
 NAIK_FULL, NAIK_R14, NAIK_R13, NAIK_R9 = 0, 1, 2, 3
 MODE_FP64, MODE_MIXED = 0, 1
 LAYOUT_SITE, LAYOUT_COLOUR = 0, 1
-K_PUPDATE, K_DSLASH_OE, K_DSLASH_EO, K_RELIABLE = 0, 1, 2, 3
+K_PUPDATE, K_DSLASH_OE, K_DSLASH_EO, K_RELIABLE, K_FORCE = 0, 1, 2, 3, 4
+K_COUNT = 5
 
 
 class Geom(ctypes.Structure):
@@ -54,7 +55,8 @@ class Info(ctypes.Structure):
                 ("eo_rhs_per_thread", ctypes.c_int32), ("eo_tile_order", ctypes.c_int32),
                 ("eo_stage_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seconds", ctypes.c_double),
-                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_int32 * 4)]
+                ("kernel_ms", ctypes.c_double * K_COUNT),
+                ("kernel_launches", ctypes.c_int32 * K_COUNT)]
 
     def to_dict(self, nrhs):
         return {

@@ -141,3 +141,32 @@ def test_config5_gradient_24x6(mode):
     euler = float(np.real(np.vdot(gU, U) + np.vdot(gN, N))) + m * gm
     say("euler", euler, -2 * loss)
     assert abs(euler + 2 * loss) <= 1e-6 * abs(loss)
+
+
+@pytest.mark.parametrize("naik", ["r14", "r9"])
+def test_autograd_mixed_compressed_naik(naik):
+    """HisqSolve in mixed precision with compressed FP32 Naik links (the forward
+    and adjoint solves iterate on them, the force runs in FP64): the gradients
+    through torch.autograd equal the oracle's force for the oracle's x and y."""
+    H = gpu_lib()
+    import torch
+    from paper_1411_4439_amd.autograd import HisqSolve
+    nk = {"r14": H.NAIK_R14, "r9": H.NAIK_R9}[naik]
+    L, m, n = (4, 4, 4, 4), 0.05, 2
+    U, N = W.make_links(L, 0.3, 221)
+    eta = W.make_sources(L, n, 222)
+    phi = W.make_sources(L, n, 223)
+    Ut = dev(U).requires_grad_(True)
+    Nt = dev(N).requires_grad_(True)
+    mt = torch.tensor(m, dtype=torch.float64, requires_grad=True)
+    x = HisqSolve.apply(Ut, Nt, mt, dev(eta), L, H.MODE_MIXED, nk, 1e-12)
+    loss = torch.real(torch.sum(torch.conj(dev(phi)) * x))
+    loss.backward()
+    xo, _ = oracle.cg(L, U, N, m, eta, tol=1e-13)
+    yo, _ = oracle.cg(L, U, N, m, phi, tol=1e-13)
+    GU, GN, dm = oracle.force(L, U, N, m, xo, yo)
+    eU = np.linalg.norm(host(Ut.grad) - GU) / np.linalg.norm(GU)
+    eN = np.linalg.norm(host(Nt.grad) - GN) / np.linalg.norm(GN)
+    say(naik, eU, eN, float(mt.grad), dm)
+    assert eU <= 1e-7 and eN <= 1e-7
+    assert abs(float(mt.grad) - dm) <= 1e-7 * abs(dm)

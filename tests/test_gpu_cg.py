@@ -391,3 +391,46 @@ def test_concurrent_solves_from_two_threads():
     assert not errors, errors
     for j in range(2):
         assert got[j] is not None and np.array_equal(got[j], ref[j]), j
+
+
+def test_batched_workload_at_its_own_sizes():
+    """The batched workload exactly as the benchmark runs it: 16^3 x 4 (3 rhs),
+    24^3 x 6 (5 rhs) and 32^3 x 8 (8 rhs), each at m = 0.05 and 0.01, links
+    with eps = 0.3, the benchmark's seeds, mixed precision with r14 Naik links,
+    all six in one batched solve.  Every rhs reaches the oracle's FP64 true
+    residual <= 1e-10, and every solution agrees with the same problem solved
+    on its own within 1e-7 (or the a-posteriori bound of the two residuals)."""
+    H = gpu_lib()
+    import torch
+    probs, keep = [], []
+    j = 0
+    for L, n in W.BATCHED_PROBLEMS:
+        for m in W.BATCHED_MASSES:
+            U, N = W.make_links(L, 0.3, W.links_seed(4, j))
+            links = H.Links(L, dev(U), dev(N), f32=False, r14=True)
+            b = W.make_sources(L, n, W.sources_seed(4, j))
+            bd = dev(b)
+            x = torch.empty_like(bd)
+            keep.append((L, n, m, U, N, b, links, bd, x))
+            probs.append(H.Problem(H.geom(L), m, n, links.f64.data_ptr(),
+                                   links.f32r14.data_ptr(), bd.data_ptr(), x.data_ptr()))
+            j += 1
+    p = H.hisq_default_params(mode=H.MODE_MIXED, naik=H.NAIK_R14)
+    ws = H.empty_bytes(H.hisq_batched_workspace_bytes(probs, H.MODE_MIXED))
+    status, infos = H.hisq_cg_solve_batched(probs, p, ws)
+    say("batched workload", status, [i.total_iters for i in infos])
+    assert status == H.HISQ_OK
+    for j, (L, n, m, U, N, b, links, bd, x) in enumerate(keep):
+        xb = host(x)
+        res = oracle.residual(L, U, N, m, b, xb)
+        xs, st, info = H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        assert st == H.HISQ_OK
+        xs = host(xs)
+        rs = oracle.residual(L, U, N, m, b, xs)
+        say("problem", j, L, n, m, "true residual", res.max(), "separate", rs.max())
+        assert res.max() <= 1e-10, (j, res)
+        for k in range(n):
+            err = np.linalg.norm(xb[..., k] - xs[..., k]) / np.linalg.norm(xs[..., k])
+            # both solutions are within ||b - A x|| / (4 m^2) of the exact one
+            bound = (res[k] + rs[k]) * np.linalg.norm(b[..., k]) / (4 * m * m) / np.linalg.norm(xs[..., k])
+            assert err <= max(1e-7, bound), (j, k, err, bound)

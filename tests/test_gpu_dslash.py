@@ -145,6 +145,91 @@ def test_pack_rejects_non_unitary_naik(naik):
     assert e.value.code == H.HISQ_EPACK
 
 
+@pytest.mark.parametrize("naik", ["r14", "r13"])
+def test_pack_rejects_naik_links_off_by_1e8(naik):
+    """r14 / r13 fit row 2 from rows 0 and 1 in FP64: a Naik link that misses
+    s*U(3) by 1e-8 of its norm is rejected, the synthetic links (exact to
+    rounding) are accepted, and a buffer that failed packing is refused
+    afterwards by the Dslash."""
+    H = gpu_lib()
+    nk = {"r14": H.NAIK_R14, "r13": H.NAIK_R13}[naik]
+    L = (4, 4, 4, 4)
+    U, N = W.make_links(L, 0.3, 5)
+    buf = H.empty_bytes(H.hisq_links_bytes(L, H.PREC_F32, nk))
+    H.hisq_pack_links(L, dev(U), dev(N), H.PREC_F32, nk, buf)
+    Nb = N.copy()
+    Nb[1, 40, 2, 1] += 1e-8 * np.linalg.norm(N[1, 40])
+    with pytest.raises(H.HisqError) as e:
+        H.hisq_pack_links(L, dev(U), dev(Nb), H.PREC_F32, nk, buf)
+    assert e.value.code == H.HISQ_EPACK
+    v = dev(_source(L, 2, 11).astype(np.complex64))
+    with pytest.raises(H.HisqError) as e:
+        H.hisq_dslash(L, 1, 2, H.PREC_F32, nk, H.LAYOUT_SITE, buf, v, v.clone())
+    assert e.value.code == H.HISQ_EINVAL
+
+
+def test_entry_points_check_the_packed_link_header():
+    """Links are only accepted for the lattice, precision and Naik storage they
+    were packed for: a mismatch in any of them, or a buffer that holds no
+    packed links, is HISQ_EINVAL before anything is launched, at the Dslash,
+    the solver, the full-matrix solve, the mu-derivative Dslash and the batched
+    solver; the matching call still works."""
+    H = gpu_lib()
+    import torch
+    L, n = (8, 8, 4, 4), 2
+    U, N = W.make_links(L, 0.3, 7)
+    links = H.Links(L, dev(U), dev(N), r13=True)
+    v64 = dev(_source(L, n, 12))
+    v32 = v64.to(torch.complex64)
+    bad = []
+    # wrong Naik storage, precision, lattice; not a packed buffer at all
+    junk = torch.zeros_like(links.f32r14)
+    Lbig = (8, 8, 8, 4)
+    vbig = dev(_source(Lbig, n, 13))
+    for args in ((L, H.PREC_F32, H.NAIK_FULL, links.f32r14, v32),
+                 (L, H.PREC_F32, H.NAIK_R14, links.f32r13, v32),
+                 (L, H.PREC_F64, H.NAIK_FULL, links.f32, v64),
+                 (L, H.PREC_F32, H.NAIK_FULL, links.f64, v32),
+                 (L, H.PREC_F32, H.NAIK_R14, junk, v32),
+                 (Lbig, H.PREC_F64, H.NAIK_FULL, links.f64, vbig.to(torch.complex128))):
+        Lc, prec, nk, buf, vin = args
+        with pytest.raises(H.HisqError) as e:
+            H.hisq_dslash(Lc, 1, n, prec, nk, H.LAYOUT_SITE, buf, vin, vin.clone())
+        bad.append(e.value.code)
+    # solver: links32 packed r14 but params say r13; links64 given an FP32 buffer
+    ws = H.empty_bytes(H.hisq_workspace_bytes(L, n, H.MODE_MIXED))
+    x = torch.empty_like(v64)
+    for l64, l32, nk in ((links.f64, links.f32r14, H.NAIK_R13), (links.f32, links.f32r14, H.NAIK_R14)):
+        p = H.hisq_default_params(mode=H.MODE_MIXED, naik=nk)
+        with pytest.raises(H.HisqError) as e:
+            H.hisq_cg_solve(L, 0.1, n, p, l64, l32, v64, x, ws)
+        bad.append(e.value.code)
+    with pytest.raises(H.HisqError) as e:
+        H.hisq_dslash_dmu(Lbig, 1, n, 1, links.f64, vbig, vbig.clone())
+    bad.append(e.value.code)
+    eo = dev(_source(L, n, 14))
+    swapped = H.Links.__new__(H.Links)
+    swapped.__dict__.update(links.__dict__)
+    swapped.f32r14 = links.f32r13  # an r13 buffer handed over as r14
+    with pytest.raises(H.HisqError) as e:
+        H.solve_full(swapped, 0.1, v64, eo, mode=H.MODE_MIXED, naik=H.NAIK_R14)
+    bad.append(e.value.code)
+    prob = H.Problem(H.geom(L), 0.1, n, links.f64.data_ptr(), links.f32r13.data_ptr(),
+                     v64.data_ptr(), x.data_ptr())
+    p = H.hisq_default_params(mode=H.MODE_MIXED, naik=H.NAIK_R14)
+    wsb = H.empty_bytes(H.hisq_batched_workspace_bytes([prob], H.MODE_MIXED))
+    with pytest.raises(H.HisqError) as e:
+        H.hisq_cg_solve_batched([prob], p, wsb)
+    bad.append(e.value.code)
+    say("rejections", bad)
+    assert all(c == H.HISQ_EINVAL for c in bad), bad
+    # the matching calls run
+    out = H.dslash(links, 1, v32, H.PREC_F32, H.NAIK_R14)
+    assert torch.isfinite(torch.view_as_real(out)).all()
+    _, st, _ = H.solve(links, 0.1, v64, mode=H.MODE_MIXED, naik=H.NAIK_R13)
+    assert st == H.HISQ_OK
+
+
 def test_dslash_headline_lattice_sampled_sites():
     """48^3 x 12, n = 8, FP32 and r14, in the autotuned launch shape and the
     colour-major order the solver and the benchmark use (and site-major):
