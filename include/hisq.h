@@ -332,6 +332,27 @@ int hisq_set_tuning(int mode, int rhs_per_thread, int block_size, int tile_order
  */
 int hisq_set_tuning_eo(int rhs_per_thread, int block_size, int tile_order, int stage_rows);
 
+/*
+ * For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc) and so cannot provide
+ * the workspace of hisq_cg_solve: the same solve, with the same arguments
+ * except the workspace, whose scratch (CG scalars, reduction partials and
+ * counters, working fields) lives in a static device array of
+ * HISQ_NOALLOC_SCRATCH_BYTES per GPU, held from library load to process end.
+ * A solve whose hisq_workspace_bytes() exceeds that returns HISQ_EWORKSPACE
+ * (64 MiB: e.g. 24^3 x 6 with up to 5 rhs in MIXED mode, 32^3 x 8 with one).
+ * It calls no hipMalloc, hipFree or other allocating routine: poll blocks run
+ * without a hipGraph (params->use_graph and ->profile are ignored) and the
+ * host copies of the CG state are the calling thread's ordinary memory.  All
+ * calls on one GPU share its array: calls that overlap in time on one GPU
+ * (from several threads or streams) race and must be serialised by the
+ * caller.  Every region that must start at zero is cleared by each call.
+ */
+#define HISQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hisq_cg_solve_noalloc(const hisq_geom* g, double mass, int nrhs, const hisq_params* p,
+                          const void* links64, const void* links32, const double* b_e,
+                          double* x_e, hisq_info* info, void* stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* hisq_last_error(void);
 

@@ -25,7 +25,8 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
 
 DSLASH_VARIANTS = [(0, 0), (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2), (2, 0), (2, 1), (2, 2),
                    (3, 0), (3, 1), (3, 2), (4, 0), (4, 1), (4, 2)]
-OTHER_SOURCES = ["blas.hip", "pack.hip", "force.hip", "dmu.hip", "dispatch.cpp", "api.cpp"]
+OTHER_SOURCES = ["blas.hip", "pack.hip", "force.hip", "dmu.hip", "dispatch.cpp", "api.cpp",
+                 "noalloc.hip"]
 
 
 def _jobs():

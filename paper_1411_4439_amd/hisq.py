@@ -114,6 +114,9 @@ _sig = {
                                            ctypes.POINTER(Params), _P, _P, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_int), _P, _P, _P, _P,
                                            ctypes.c_size_t, ctypes.POINTER(Info), _P]),
+    "hisq_cg_solve_noalloc": (ctypes.c_int, [_G, ctypes.c_double, ctypes.c_int,
+                                             ctypes.POINTER(Params), _P, _P, _P, _P,
+                                             ctypes.POINTER(Info), _P]),
     "hisq_last_error": (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _sig.items():
@@ -216,6 +219,16 @@ def hisq_cg_solve(L, mass, nrhs, params, links64, links32, b, x, ws, info=None, 
                             _ptr(links64), _ptr(links32), _ptr(b), _ptr(x), _ptr(ws),
                             ws.numel() * ws.element_size(), ctypes.byref(info), _stream(stream))
     return _check(rc, "hisq_cg_solve"), info
+
+
+def hisq_cg_solve_noalloc(L, mass, nrhs, params, links64, links32, b, x, info=None, stream=None):
+    _dev_tensor(b, "b")
+    _dev_tensor(x, "x")
+    info = info if info is not None else Info()
+    rc = _lib.hisq_cg_solve_noalloc(ctypes.byref(geom(L)), float(mass), nrhs, ctypes.byref(params),
+                                    _ptr(links64), _ptr(links32), _ptr(b), _ptr(x),
+                                    ctypes.byref(info), _stream(stream))
+    return _check(rc, "hisq_cg_solve_noalloc"), info
 
 
 def hisq_cg_solve_backward(L, mass, nrhs, params, links64, links32, x, grad_x, grad_U, grad_N,
