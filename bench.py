@@ -16,8 +16,14 @@ The JSON line reports
   roofline       the dominant kernel's achieved GB/s against 8 TB/s,
   cg             time-to-solution of the step against 8 sequential FP64 1-rhs
                  solves of the same sources (same GPU), iterations, residuals,
+  accuracy       per-rhs true residual and the a-posteriori solution-error bound,
   dslash_sweep   standalone Dslash GB/s for n = 1, 2, 4, 8 (FP64, FP32, r14, r13, r9),
-  cpu_baseline   the FP64 CPU oracle's Dslash on the host cores (a bounded sample).
+  full_and_trace the full-matrix solve and one bundle of eq. (2) trace terms,
+  config2        32^3 x 8: Dslash sweep and CG time against bundle size,
+  backward       24^3 x 6 gradient: adjoint solve and link-force kernel,
+  batched        six solves in one launch per CG phase against six separate ones,
+  cpu_baseline   the FP64 CPU oracle on the host cores: Dslash rates, full CGs,
+                 and one headline rhs to 1e-13 (the headline's error against it).
 """
 from __future__ import annotations
 
@@ -56,6 +62,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-trace", action="store_true")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the 32^3 x 8 Dslash sweep and CG bundle gains")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip the 24^3 x 6 gradient (adjoint solve + link force) timing")
+    ap.add_argument("--no-oracle-cg", action="store_true",
+                    help="skip the oracle's FP64 CG runs in the CPU baseline (the longest part)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--tile", default=DEFAULT_TILE,
                     help="tile of the solve's D_oe Dslash (and p-update): "
@@ -112,6 +124,219 @@ def measured_traffic(kernel, workload, tile):
                 and "traffic_bytes_per_launch" in kv):
             return float(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
     return None, None
+
+
+_LINKS = {}
+
+
+def links_of(W, L, eps, seed):
+    """Seeded canonical links, generated once per (lattice, eps, seed) in this run."""
+    key = (tuple(L), eps, seed)
+    if key not in _LINKS:
+        _LINKS[key] = W.make_links(L, eps, seed)
+    return _LINKS[key]
+
+
+def median_event_ms(fn, stream, reps, warm=5):
+    """Median duration of `reps` launches of fn, each between its own pair of
+    HIP events on `stream`, after `warm` untimed launches."""
+    import torch
+    for _ in range(warm):
+        fn()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(stream)
+    for r in range(reps):
+        fn()
+        evs[r + 1].record(stream)
+    evs[-1].synchronize()
+    return float(np.median([evs[r].elapsed_time(evs[r + 1]) for r in range(reps)]))
+
+
+def config2_block(H, R, W, dev, stream):
+    """32^3 x 8, m = 0.02: standalone Dslash at n = 1, 2, 4, 8 (FP64, FP32, FP32
+    with r14 Naik links), and CG time-to-solution at n = 1, 2, 4, 8, mixed r14 and
+    FP64, with the bundle gain n * t(1) / t(n) (the paper's 4-rhs over 1-rhs gain
+    is about 2.05, against the 2.16 of its Dslash intensity, Sec. 3)."""
+    import torch
+    L, m = (32, 32, 32, 8), 0.02
+    Vh = W.half_volume(L)
+    U, N = links_of(W, L, 0.3, W.links_seed(2))
+    links = H.Links(L, dev(U), dev(N))
+    b8 = W.make_sources(L, 8, W.sources_seed(2))
+    H.hisq_set_tuning(0)
+    sweep = {}
+    for prec, nk, tag in ((H.PREC_F64, H.NAIK_FULL, "f64"), (H.PREC_F32, H.NAIK_FULL, "f32"),
+                          (H.PREC_F32, H.NAIK_R14, "f32_r14")):
+        dt = torch.complex128 if prec == H.PREC_F64 else torch.complex64
+        for nn in (1, 2, 4, 8):
+            vin = dev(b8[:, :, :nn]).to(dt).permute(1, 0, 2).contiguous()
+            vout = torch.empty_like(vin)
+            packed = links.packed(prec, nk)
+            ms = median_event_ms(lambda: H.hisq_dslash(L, 1, nn, prec, nk, H.LAYOUT_COLOUR, packed,
+                                                       vin, vout), stream, 100, warm=10)
+            scale = 2 if prec == H.PREC_F64 else 1
+            byt = Vh * scale * (R.LINK_BYTES_F32["r14" if nk == H.NAIK_R14 else "full"]
+                                + 2 * R.VEC_BYTES_F32 * nn)
+            sweep["%s_n%d" % (tag, nn)] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
+                                           "pct_hbm_peak": round(byt / ms / 1e6 / HBM_PEAK_GBPS * 100, 1)}
+    cg = {}
+    for mode, nk, tag in ((H.MODE_MIXED, H.NAIK_R14, "mixed_r14"), (H.MODE_FP64, H.NAIK_FULL, "fp64")):
+        per = {}
+        for nn in (1, 2, 4, 8):
+            bd = dev(b8[:, :, :nn])
+            ws = H.empty_bytes(H.hisq_workspace_bytes(L, nn, mode))
+            H.solve(links, m, bd, mode=mode, naik=nk, ws=ws)  # tune + warm
+            torch.cuda.synchronize()
+            best = 1e30
+            for _ in range(2):
+                t0 = time.perf_counter()
+                _, st, info = H.solve(links, m, bd, mode=mode, naik=nk, ws=ws)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            if st != H.HISQ_OK:
+                raise SystemExit("config2 solve failed: %s" % info)
+            per[nn] = {"seconds": round(best, 4), "seconds_per_rhs": round(best / nn, 4),
+                       "iters_max": max(info["iters"]),
+                       "rel_true_res_max": max(info["rel_true_res"])}
+        for nn in (2, 4, 8):
+            per[nn]["gain_vs_1rhs"] = round(nn * per[1]["seconds"] / per[nn]["seconds"], 2)
+        cg[tag] = {"n%d" % k: v for k, v in per.items()}
+    cg["paper_4rhs_gain"] = "about 2.05 (95% of the 2.16 Dslash intensity gain), Sec. 3, single precision"
+    return {"workload": "32x32x32x8, m=0.02, eps=0.3, colour-major fields, autotuned tiles",
+            "dslash_sweep": sweep, "cg": cg}
+
+
+def backward_block(H, W, dev):
+    """24^3 x 6, n = 4, m = 0.05: the forward solve, then the backward (adjoint
+    solve on the same operator, two FP64 half-Dslash, the link-force kernel and
+    dL/dm), in FP64 and in mixed precision with r14 Naik links; the link-force
+    kernel's algorithmic GB/s: it reads x, y (even) and D_oe x, D_oe y (odd), each
+    once, and writes dL/dU and dL/dN, V (1152 + 96 n) bytes."""
+    import torch
+    L, m, n = (24, 24, 24, 6), 0.05, 4
+    V = W.volume(L)
+    U, N = W.make_links(L, 0.3, W.links_seed(5))
+    links = H.Links(L, dev(U), dev(N))
+    eta = dev(W.make_sources(L, n, W.sources_seed(5)))
+    phi = dev(W.make_sources(L, n, W.sources_seed(5, 1)))
+    H.hisq_set_tuning(0)
+    out = {"workload": "24x24x24x6, n=4, m=0.05, eps=0.3; L = sum_k Re(phi_k^dag x_k)"}
+    force_bytes = V * (1152 + 96 * n)
+    for mode, nk, tag in ((H.MODE_FP64, H.NAIK_FULL, "fp64"), (H.MODE_MIXED, H.NAIK_R14, "mixed_r14")):
+        gU = torch.empty((4, V, 3, 3), dtype=torch.complex128, device="cuda")
+        gN = torch.empty_like(gU)
+        gm = torch.zeros((), dtype=torch.float64, device="cuda")
+        gb = torch.empty_like(eta)
+        wsb = H.empty_bytes(H.hisq_backward_workspace_bytes(L, n, mode))
+        l32 = links.packed(H.PREC_F32, nk) if mode == H.MODE_MIXED else None
+        x, st, info = H.solve(links, m, eta, mode=mode, naik=nk)  # tune + warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, info = H.solve(links, m, eta, mode=mode, naik=nk)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+
+        def bwd(profile=0):
+            p = H.hisq_default_params(mode=mode, naik=nk, profile=profile)
+            return H.hisq_cg_solve_backward(L, m, n, p, links.f64, l32, x, phi, gU, gN, gm, gb, wsb)
+        bwd()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stb, infb = bwd()
+        torch.cuda.synchronize()
+        t_bwd = time.perf_counter() - t0
+        fms = []
+        for _ in range(5):
+            _, infp = bwd(profile=1)
+            fms.append(infp.kernel_ms[H.K_FORCE])
+        f_ms = float(np.median(fms))
+        out[tag] = {"forward_seconds": round(t_fwd, 4), "forward_iters_max": max(info["iters"]),
+                    "backward_seconds": round(t_bwd, 4), "adjoint_iters_max": infb.total_iters,
+                    "adjoint_solve_seconds": round(infb.seconds, 4), "status": stb,
+                    "force_kernel_ms": round(f_ms, 4),
+                    "force_kernel_GBps": round(force_bytes / f_ms / 1e6, 1),
+                    "force_algorithmic_bytes": force_bytes}
+    return out
+
+
+def cpu_baseline(args, W, R, L, U, N, b, n, m, Vh, iters, ms_per_step, x_head0):
+    """The FP64 CPU oracle, as it stands, on the host cores: half-Dslash rates on
+    the 48^3 x 12 workload (all threads and one), on 8^4 and 32^3 x 8 at n = 1, 2,
+    4, 8; full oracle CGs on 8^4 (n = 1) and 32^3 x 8 (n = 1 and 8) to relative
+    residual 1e-10; and one rhs of the 48^3 x 12 headline to 1e-13, whose
+    solution gives the headline's error against the oracle."""
+    import oracle
+    import platform
+
+    def timed(fn, seconds, cap=1000):
+        t0c = time.perf_counter()
+        k = 0
+        while True:
+            fn()
+            k += 1
+            if time.perf_counter() - t0c > seconds or k >= cap:
+                return k, (time.perf_counter() - t0c) / k
+
+    vh = b[:, :, :n]
+    threads = oracle.num_threads()
+    reps, cpu_s = timed(lambda: oracle.dslash_eo(L, U, N, vh, 1), args.cpu_seconds * 0.3)
+    oracle.set_num_threads(1)
+    reps_1, cpu_1 = timed(lambda: oracle.dslash_eo(L, U, N, vh, 1), args.cpu_seconds * 0.1)
+    oracle.set_num_threads(threads)
+    cpu_bytes = Vh * 2 * (R.LINK_BYTES_F32["full"] + 2 * R.VEC_BYTES_F32 * n)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    res = {"value": round(cpu_bytes / cpu_s / 1e9, 3), "unit": "GB/s", "cores": threads,
+           "kind": "oracle",
+           "sample": "%d FP64 half-Dslash applications, %s, %d rhs (%.3f s each)"
+                     % (reps, "x".join(map(str, L)), n, cpu_s),
+           "cpu_model": model or platform.processor(), "nproc": os.cpu_count(),
+           "one_thread_GBps": round(cpu_bytes / cpu_1 / 1e9, 3)}
+    # Dslash on 8^4 and 32^3 x 8, all threads and one thread
+    table = {}
+    for Lc, seed in (((8, 8, 8, 8), W.links_seed(1)), ((32, 32, 32, 8), W.links_seed(2))):
+        Uc, Nc = links_of(W, Lc, 0.3, seed)
+        bc = W.make_sources(Lc, 8, seed + 500)
+        vhc = W.half_volume(Lc)
+        for nn in (1, 2, 4, 8):
+            v = np.ascontiguousarray(bc[:, :, :nn])
+            byt = vhc * 2 * (R.LINK_BYTES_F32["full"] + 2 * R.VEC_BYTES_F32 * nn)
+            row = {}
+            for th in (threads, 1):
+                oracle.set_num_threads(th)
+                k, sec = timed(lambda: oracle.dslash_eo(Lc, Uc, Nc, v, 1), 0.25, cap=200)
+                row["GBps_%dthreads" % th] = round(byt / sec / 1e9, 3)
+            oracle.set_num_threads(threads)
+            table["%s_n%d" % ("x".join(map(str, Lc)), nn)] = row
+    res["dslash_GBps"] = table
+    if not args.no_oracle_cg:
+        cgs = {}
+        for Lc, mc, nn, cfg in (((8, 8, 8, 8), 0.1, 1, 1), ((32, 32, 32, 8), 0.02, 1, 2),
+                                ((32, 32, 32, 8), 0.02, 8, 2)):
+            Uc, Nc = links_of(W, Lc, 0.3, W.links_seed(cfg))
+            bc = np.ascontiguousarray(W.make_sources(Lc, 8, W.sources_seed(cfg))[:, :, :nn])
+            t0c = time.perf_counter()
+            _, inf = oracle.cg(Lc, Uc, Nc, mc, bc, tol=1e-10)
+            cgs["%s_n%d" % ("x".join(map(str, Lc)), nn)] = {
+                "seconds": round(time.perf_counter() - t0c, 3), "iters_max": int(max(inf["iters"])),
+                "true_res_max": float(max(inf["true_res"]))}
+        # one rhs of the headline, to 1e-13: measured CG time and the GPU's error
+        t0c = time.perf_counter()
+        xo, inf = oracle.cg(L, U, N, m, np.ascontiguousarray(b[:, :, :1]), tol=1e-13)
+        t_o = time.perf_counter() - t0c
+        err = float(np.linalg.norm(x_head0 - xo[:, :, 0]) / np.linalg.norm(xo[:, :, 0]))
+        cgs["%s_n1_tol1e-13" % "x".join(map(str, L))] = {
+            "seconds": round(t_o, 2), "iters": int(inf["iters"][0]),
+            "true_res": float(inf["true_res"][0])}
+        res["cg"] = cgs
+        res["headline_rhs0_error_vs_oracle"] = float("%.3e" % err)
+        res["gpu_seconds_per_rhs"] = round(ms_per_step / 1e3 / n, 4)
+    return res
+
 
 
 def main():
@@ -255,6 +480,18 @@ def main():
                            "block": infos[-1]["eo_block_size"], "order": infos[-1]["eo_tile_order"],
                            "stage_rows": infos[-1]["eo_stage_rows"]}},
     }
+    # accuracy of the headline solution: the a-posteriori bound
+    # ||x - x*|| / ||x|| <= ||b - A x|| / (4 m^2 ||x||), since lambda_min(A) >= 4 m^2
+    # (the oracle's own solution error for one rhs is added by the CPU-baseline leg)
+    xnorm = torch.linalg.vector_norm(x, dim=(0, 1)).cpu().numpy()
+    bnorm = torch.linalg.vector_norm(bd, dim=(0, 1)).cpu().numpy()
+    rel_true = np.array(infos[-1]["rel_true_res"])
+    result["accuracy"] = {
+        "rel_true_res": [float("%.3e" % v) for v in rel_true],
+        "error_bound": [float("%.3e" % v) for v in rel_true * bnorm / (4 * m * m * xnorm)],
+        "bound_note": "||x - x*|| / ||x|| <= ||b - A x|| / (4 m^2 ||x||) per rhs"}
+    x_head0 = x[:, :, 0].cpu().numpy()
+
     # the comparison solver and the standalone sweep use the autotuner's tiles
     H.hisq_set_tuning(0)
 
@@ -380,6 +617,14 @@ def main():
         log("full/trace", json.dumps(result["full_and_trace"]))
         del wsf, ee, eo, vo
 
+    if not args.no_config2:
+        result["config2"] = config2_block(H, R, W, dev, stream)
+        log("config2", json.dumps(result["config2"]))
+
+    if not args.no_backward:
+        result["backward"] = backward_block(H, W, dev)
+        log("backward", json.dumps(result["backward"]))
+
     if not args.no_batched:
         # config 4: six solves (three lattices x two masses, bundles of 3, 5, 8)
         # in one batched launch per CG phase, against the same six solved one by one
@@ -405,6 +650,12 @@ def main():
         stb, infb = H.hisq_cg_solve_batched(probs, pb, wsb)
         torch.cuda.synchronize()
         t_batched = time.perf_counter() - tb
+        pprof = H.hisq_default_params(mode=H.MODE_MIXED, naik=H.NAIK_R14, profile=1)
+        _, infp = H.hisq_cg_solve_batched(probs, pprof, wsb)
+        it_b = max(i.total_iters for i in infp)
+        phase_ms = {name: round(infp[0].kernel_ms[c] / max(it_b, 1), 5)
+                    for name, c in (("pupdate", H.K_PUPDATE), ("dslash_oe_norm", H.K_DSLASH_OE),
+                                    ("dslash_eo_cg_epilogue", H.K_DSLASH_EO))}
         ts = time.perf_counter()
         sep_iters = []
         for Lb, nb, mb, lb, bb, xb in keep:
@@ -418,53 +669,16 @@ def main():
                              "status": stb, "batched_seconds": round(t_batched, 4),
                              "separate_seconds": round(t_sep, 4),
                              "speedup": round(t_sep / t_batched, 2),
-                             "iters": [i.total_iters for i in infb], "separate_iters": sep_iters}
+                             "iters": [i.total_iters for i in infb], "separate_iters": sep_iters,
+                             "per_iteration_kernel_ms": phase_ms,
+                             "block_size": infb[0].block_size,
+                             "rhs_per_thread": [i.rhs_per_thread for i in infb]}
         log("batched", json.dumps(result["batched"]))
         del keep, probs, wsb
 
     if not args.no_cpu_baseline:
-        import oracle
-        import platform
-        vh = b[:, :, :n]
-
-        def timed(fn, seconds):
-            t0c = time.perf_counter()
-            k = 0
-            while True:
-                fn()
-                k += 1
-                if time.perf_counter() - t0c > seconds or k >= 1000:
-                    return k, (time.perf_counter() - t0c) / k
-
-        # the oracle's FP64 half-Dslash on all host threads (about 2/3 of the
-        # CPU budget), its A = 4m^2 - D_eo D_oe (one CG iteration's operator)
-        reps, cpu_s = timed(lambda: oracle.dslash_eo(L, U, N, vh, 1), args.cpu_seconds * 0.6)
-        reps_a, cpu_a = timed(lambda: oracle.apply_A(L, U, N, m, vh), args.cpu_seconds * 0.25)
-        threads = oracle.num_threads()
-        oracle.set_num_threads(1)
-        reps_1, cpu_1 = timed(lambda: oracle.dslash_eo(L, U, N, vh, 1), args.cpu_seconds * 0.15)
-        oracle.set_num_threads(threads)
-        cpu_bytes = Vh * 2 * (R.LINK_BYTES_F32["full"] + 2 * vec_b * n)
-        model = ""
-        try:
-            with open("/proc/cpuinfo") as fh:
-                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
-        except OSError:
-            pass
-        gpu_iter_s = ms_per_step / 1e3 / max(1, max(iters))
-        result["cpu_baseline"] = {"value": round(cpu_bytes / cpu_s / 1e9, 3), "unit": "GB/s",
-                                  "cores": threads, "kind": "oracle",
-                                  "sample": "%d FP64 half-Dslash applications, %s, %d rhs (%.3f s each)"
-                                            % (reps, "x".join(map(str, L)), n, cpu_s),
-                                  "cpu_model": model or platform.processor(),
-                                  "nproc": os.cpu_count(),
-                                  "one_thread_GBps": round(cpu_bytes / cpu_1 / 1e9, 3),
-                                  "cg_iteration_seconds": round(cpu_a, 4),
-                                  "cg_solve_seconds_extrapolated": round(cpu_a * max(iters), 1),
-                                  "cg_note": "A applied %d times (%.3f s each); a full solve "
-                                             "extrapolated to the GPU's %d iterations; the GPU "
-                                             "needs %.5f s per iteration" % (reps_a, cpu_a, max(iters),
-                                                                          gpu_iter_s)}
+        result["cpu_baseline"] = cpu_baseline(args, W, R, L, U, N, b, n, m, Vh, iters, ms_per_step,
+                                              x_head0)
     print(json.dumps(result), flush=True)
 
     if args.copy_calibration:

@@ -30,29 +30,35 @@ __device__ __forceinline__ void pupdate_tile(const PupdateArgs<T>& a, int tile, 
         part[k] = 0.0;
     }
     const int i = (tile * (int)blockDim.x + (int)threadIdx.x) / G;
-    if (i < a.lat.Vh && any_act) {
-        using Lay = Layout<NRHS, true>;
-        const int base = Lay::site(i) + g * NR;
+    const bool work = i < a.lat.Vh && any_act;
+    using Lay = Layout<NRHS, true>;
+    const int base = Lay::site(work ? i : 0) + g * NR;
+    C pv[3][NR];
+    if (work) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const int off = base + Lay::colour(c, a.lat.Vh);
-            // converged (masked) rhs are not written
-            C rv[NR], pv[NR];
+            C rv[NR];
             load_rhs<NR>(a.r + off, rv);
-            load_rhs<NR>(a.p + off, pv);
+            load_rhs<NR>(a.p + off, pv[c]);
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
                 // beta = 0 starts (or restarts) the recursion: p = r exactly, even
                 // if p held non-finite values
-                pv[k] = beta[k] == T(0) ? rv[k]
-                                        : C{rv[k].x + beta[k] * pv[k].x, rv[k].y + beta[k] * pv[k].y};
-                if (act[k]) part[k] += (double)pv[k].x * pv[k].x + (double)pv[k].y * pv[k].y;
+                pv[c][k] = beta[k] == T(0) ? rv[k]
+                                           : C{rv[k].x + beta[k] * pv[c][k].x, rv[k].y + beta[k] * pv[c][k].y};
+                if (act[k]) part[k] += (double)pv[c][k].x * pv[c][k].x + (double)pv[c][k].y * pv[c][k].y;
             }
-            store_rhs_on<NR>(a.p + off, pv, act);
         }
     }
+    // partials first, then the stores (converged rhs are not written)
+    const bool last = grid_reduce_post<NRHS, NR>(part, a.red, a.cnt, nblk, bid);
+    if (work) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) store_rhs_on<NR>(a.p + base + Lay::colour(c, a.lat.Vh), pv[c], act);
+    }
     double total;
-    if (grid_reduce_rhs<NRHS, NR>(part, a.red, a.cnt, nblk, bid, &total)) {
+    if (last && grid_reduce_finish<NRHS>(a.red, a.cnt, nblk, bid, &total)) {
         if (threadIdx.x < NRHS && !a.state->frozen) a.state->pp[threadIdx.x] = total;
     }
 }

@@ -467,8 +467,17 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
         stage_rows<T, NRHS>(a.in, lds, a.lat, tile * a.rows, a.rows);
         __syncthreads();
     }
-    if (i < a.lat.Vh) {
-        C acc[3][NR];
+    // The epilogue computes everything before its stores, posts the
+    // work-group's reduction partials, and only then stores the outputs: the
+    // completion wait that orders the partials before the counter update does
+    // not wait for the output stores.
+    const bool on_site = i < a.lat.Vh;
+    using Lay = Layout<NRHS, CM>;
+    const int base = Lay::site(on_site ? i : 0) + g * NR;
+    C acc[3][NR];
+    C xo[3][NR], ro[3][NR];  // EPI_CG: updated x and r
+    d2 rr[3][NR];            // EPI_RESID: the FP64 residual
+    if (on_site) {
         if constexpr (ST)
             dslash_site_lds<T, NRHS, NR, NK>(a.lat, a.parity, i, g,
                                               ((int)threadIdx.x / G) / a.lat.Lh0, a.links, a.in,
@@ -476,17 +485,11 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
         else
             dslash_site<T, NRHS, NR, NK, CM>(a.lat, a.parity, i, g, a.links, a.in, acc, ns);
         pin_acc(acc);
-        using Lay = Layout<NRHS, CM>;
-        const int base = Lay::site(i) + g * NR;
-        if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM) {
+        if constexpr (EPI == EPI_NORM) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                store_rhs<NR>(a.out + base + Lay::colour(c, a.lat.Vh), acc[c]);
-                if constexpr (EPI == EPI_NORM) {
+            for (int c = 0; c < 3; ++c)
 #pragma unroll
-                    for (int k = 0; k < NR; ++k) part[k] += norm2c<T>(acc[c][k]);
-                }
-            }
+                for (int k = 0; k < NR; ++k) part[k] += norm2c<T>(acc[c][k]);
         } else if constexpr (EPI == EPI_CG) {
             if (any_act) {
             // converged (masked) rhs are not written (and not read where the
@@ -494,21 +497,17 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
             // zero and their finisher ignores them
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                C pv[NR], xv[NR], rv[NR];
+                C pv[NR];
                 load_rhs<NR, true>(a.p + base + Lay::colour(c, a.lat.Vh), pv);
-                load_rhs<NR, true>(a.x + base + Lay::colour(c, a.lat.Vh), xv);
-                load_rhs<NR, true>(a.r + base + Lay::colour(c, a.lat.Vh), rv);
+                load_rhs<NR, true>(a.x + base + Lay::colour(c, a.lat.Vh), xo[c]);
+                load_rhs<NR, true>(a.r + base + Lay::colour(c, a.lat.Vh), ro[c]);
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
                     const C q = C{m4 * pv[k].x - acc[c][k].x, m4 * pv[k].y - acc[c][k].y};
-                    xv[k] = C{xv[k].x + alpha[k] * pv[k].x, xv[k].y + alpha[k] * pv[k].y};
-                    rv[k] = C{rv[k].x - alpha[k] * q.x, rv[k].y - alpha[k] * q.y};
-                    if (act[k]) part[k] += norm2c<T>(rv[k]);
+                    xo[c][k] = C{xo[c][k].x + alpha[k] * pv[k].x, xo[c][k].y + alpha[k] * pv[k].y};
+                    ro[c][k] = C{ro[c][k].x - alpha[k] * q.x, ro[c][k].y - alpha[k] * q.y};
+                    if (act[k]) part[k] += norm2c<T>(ro[c][k]);
                 }
-                // plain stores: L2 merges the partial lines of consecutive
-                // store instructions before they reach HBM
-                store_rhs_on<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xv, act);
-                store_rhs_on<NR>(a.r + base + Lay::colour(c, a.lat.Vh), rv, act);
             }
             }
         } else if constexpr (EPI == EPI_RESID) {
@@ -520,19 +519,44 @@ __device__ __forceinline__ void dslash_tile(const DslashArgs<T>& a, int tile, in
                 load_rhs<NR>(a.xh + base + Lay::colour(c, a.lat.Vh), xv);
 #pragma unroll
                 for (int k = 0; k < NR; ++k) {
-                    const d2 rv = d2{bv[k].x - (m4 * xv[k].x - acc[c][k].x),
-                                     bv[k].y - (m4 * xv[k].y - acc[c][k].y)};
-                    part[k] += norm2c<double>(rv);
-                    if (act[k]) a.out[base + Lay::colour(c, a.lat.Vh) + k] = rv;
+                    rr[c][k] = d2{bv[k].x - (m4 * xv[k].x - acc[c][k].x),
+                                  bv[k].y - (m4 * xv[k].y - acc[c][k].y)};
+                    part[k] += norm2c<double>(rr[c][k]);
                 }
             }
             }
         }
     }
 
+    bool last = false;
+    if constexpr (EPI != EPI_PLAIN) last = grid_reduce_post<NRHS, NR>(part, a.red, a.cnt, nblk, bid);
+
+    if (on_site) {
+        if constexpr (EPI == EPI_PLAIN || EPI == EPI_NORM) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) store_rhs<NR>(a.out + base + Lay::colour(c, a.lat.Vh), acc[c]);
+        } else if constexpr (EPI == EPI_CG) {
+            if (any_act) {
+                // plain stores: L2 merges the partial lines of consecutive
+                // store instructions before they reach HBM
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    store_rhs_on<NR>(a.x + base + Lay::colour(c, a.lat.Vh), xo[c], act);
+                    store_rhs_on<NR>(a.r + base + Lay::colour(c, a.lat.Vh), ro[c], act);
+                }
+            }
+        } else if constexpr (EPI == EPI_RESID) {
+            if (any_act) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    store_rhs_on<NR>(a.out + base + Lay::colour(c, a.lat.Vh), rr[c], act);
+            }
+        }
+    }
+
     if constexpr (EPI != EPI_PLAIN) {
         double total;
-        if (grid_reduce_rhs<NRHS, NR>(part, a.red, a.cnt, nblk, bid, &total)) {
+        if (last && grid_reduce_finish<NRHS>(a.red, a.cnt, nblk, bid, &total)) {
             if (threadIdx.x < NRHS) finish<EPI>(a.state, threadIdx.x, total, a.mass4);
         }
     }

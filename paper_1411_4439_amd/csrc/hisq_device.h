@@ -106,9 +106,14 @@ __device__ __forceinline__ double wave_sum(double v)
 // fence: on this chip an agent-scope release writes back the XCD's whole L2,
 // which one work-group per launch can afford but every work-group cannot; the
 // completion wait orders exactly the stores the reader needs.
+// Stage 1 of grid_reduce_rhs: the work-group's partials are posted and its
+// group's counter advanced.  Returns true in wave 0 of the work-group that
+// arrived last in its group of 64, which must then call grid_reduce_finish.
+// A kernel may issue stores that the reduction does not read (its output
+// fields) between the two calls, so that the completion wait before the
+// counter update covers only the partials.
 template <int NRHS, int NR>
-__device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, int nblk, int bid,
-                                double* total)
+__device__ bool grid_reduce_post(double (&part)[NR], double* red, uint32_t* cnt, int nblk, int bid)
 {
     constexpr int G = NRHS / NR;
     static_assert(G == 1 || G == 2 || G == 4 || G == 8, "rhs groups must be a power of two");
@@ -116,10 +121,6 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
-    const int ngroups = (nblk + kRedGroup - 1) / kRedGroup;
-    double* gsum = red + (size_t)nblk * NRHS;
-
-    // stage 1
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
 #pragma unroll
@@ -138,12 +139,25 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
     }
     wait_memory();
     const int grp = bid / kRedGroup;
-    const int g0 = grp * kRedGroup;
-    const int gn = min(kRedGroup, nblk - g0);
+    const int gn = min(kRedGroup, nblk - grp * kRedGroup);
     uint32_t prev = 0;
     if (lane == 0) prev = add_coherent(&cnt[1 + grp], 1u);
     prev = __shfl(prev, 0, 64);
-    if (prev != (uint32_t)(gn - 1)) return false;
+    return prev == (uint32_t)(gn - 1);
+}
+
+// Stages 2 and 3, in wave 0 of a work-group for which grid_reduce_post
+// returned true: returns true in the one work-group that finished the grid,
+// where lane k < NRHS then holds the total of rhs k in *total.
+template <int NRHS>
+__device__ bool grid_reduce_finish(double* red, uint32_t* cnt, int nblk, int bid, double* total)
+{
+    const int lane = threadIdx.x & 63;
+    const int ngroups = (nblk + kRedGroup - 1) / kRedGroup;
+    double* gsum = red + (size_t)nblk * NRHS;
+    const int grp = bid / kRedGroup;
+    const int g0 = grp * kRedGroup;
+    const int gn = min(kRedGroup, nblk - g0);
     acquire_agent();
 
     // stage 2: the last work-group of the group
@@ -160,6 +174,7 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
     if (lane < NRHS) store_coherent(&gsum[(size_t)grp * NRHS + lane], mine);
     if (lane == 0) store_coherent(&cnt[1 + grp], 0u);
     wait_memory();
+    uint32_t prev = 0;
     if (lane == 0) prev = add_coherent(&cnt[0], 1u);
     prev = __shfl(prev, 0, 64);
     if (prev != (uint32_t)(ngroups - 1)) return false;
@@ -184,6 +199,14 @@ __device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, 
     if (lane == 0) store_coherent(&cnt[0], 0u);
     *total = mine;
     return true;
+}
+
+template <int NRHS, int NR>
+__device__ bool grid_reduce_rhs(double (&part)[NR], double* red, uint32_t* cnt, int nblk, int bid,
+                                double* total)
+{
+    if (!grid_reduce_post<NRHS, NR>(part, red, cnt, nblk, bid)) return false;
+    return grid_reduce_finish<NRHS>(red, cnt, nblk, bid, total);
 }
 
 __device__ inline bool finite_d(double v) { return v - v == 0.0; }
