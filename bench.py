@@ -255,6 +255,7 @@ def backward_block(H, W, dev):
                     "adjoint_solve_seconds": round(infb.seconds, 4), "status": stb,
                     "force_kernel_ms": round(f_ms, 4),
                     "force_kernel_GBps": round(force_bytes / f_ms / 1e6, 1),
+                    "force_kernel_frac": round(force_bytes / f_ms / 1e6 / 8000.0, 3),
                     "force_algorithmic_bytes": force_bytes}
     return out
 

@@ -1624,26 +1624,31 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     const int st = solve_impl(mass, nrhs, &q, links64, links32, grad_x, (double*)y, w, info,
                               stream, lat);
     if (st < 0) return st;
-    // t = D_oe x, s = D_oe y (FP64), then one thread per link
+    // The force kernel reads colour-major fields: y is still in that order in
+    // the solver's working copy (w.xc), x is converted into the free FP64
+    // residual field (w.r64); then t = D_oe x and s = D_oe y (FP64, colour-major)
+    const d2* yc = w.xc;
+    d2* xc = w.r64;
+    HIP_TRY(launch_layout(reinterpret_cast<const d2*>(x_e), xc, lat.Vh, nrhs, true, s));
     Tile t = default_tile(nrhs, HISQ_PREC_F64);
     DslashArgs<double> a{};
     a.lat = lat;
     a.parity = 1;
     a.links = link_block<double>(links64, lat.Vh, HISQ_NAIK_FULL, 1);
-    a.in = reinterpret_cast<const d2*>(x_e);
+    a.in = xc;
     a.out = w.tx;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, false));  // caller's site-major fields
-    a.in = y;
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, true));
+    a.in = yc;
     a.out = w.sy;
-    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, false));
+    HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, true));
     hipEvent_t fe[2] = {nullptr, nullptr};
     if (p->profile) {
         HIP_TRY(hipEventCreate(&fe[0]));
         HIP_TRY(hipEventCreate(&fe[1]));
         HIP_TRY(hipEventRecord(fe[0], s));
     }
-    HIP_TRY(launch_force(lat, nrhs, reinterpret_cast<const d2*>(x_e), y, w.tx, w.sy,
-                         reinterpret_cast<d2*>(grad_U), reinterpret_cast<d2*>(grad_N), s));
+    HIP_TRY(launch_force(lat, nrhs, xc, yc, w.tx, w.sy, reinterpret_cast<d2*>(grad_U),
+                         reinterpret_cast<d2*>(grad_N), s));
     if (p->profile) HIP_TRY(hipEventRecord(fe[1], s));
     HIP_TRY(launch_redot(y, reinterpret_cast<const d2*>(x_e), lat.Vh, nrhs, -8.0 * mass, grad_m,
                          w.red, w.cnt, s));

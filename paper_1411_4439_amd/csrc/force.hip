@@ -7,8 +7,8 @@
 // that hold link (a, mu), with b = a + mu for U and b = a + 3 mu for N:
 //   a even:  G[mu][a] =  sum_k ( y_a t_b^dag + x_a s_b^dag )
 //   a odd :  G[mu][a] = -sum_k ( t_a y_b^dag + s_a x_b^dag )
-// in the convention G = dL/dRe + i dL/dIm.  One thread per link; every link
-// has one writer, so no atomics are needed.
+// in the convention G = dL/dRe + i dL/dIm.  Every link has one writer, so no
+// atomics are needed.
 #include "hisq_device.h"
 
 namespace hisq {
@@ -18,15 +18,33 @@ __device__ __forceinline__ d2 cmul_conj(d2 a, d2 b)  // a * conj(b)
     return d2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-__global__ void k_force(Lat lat, int nrhs, const d2* __restrict__ x, const d2* __restrict__ y,
-                        const d2* __restrict__ tx, const d2* __restrict__ sy, d2* __restrict__ GU,
-                        d2* __restrict__ GN)
+constexpr int kForceSites = 32;              // sites per work-group
+constexpr int kForceBlock = 4 * kForceSites;  // one thread per (direction, site)
+
+// One thread per link (mu, a).  A work-group covers the links of all four
+// directions of kForceSites consecutive canonical sites (thread = mu * 32 +
+// site), so a site's own fields, read by its four links, come from the cache
+// after the first.  Fields are colour-major, [3][Vh][n]: the rhs of one
+// colour of a site are n consecutive complex numbers; the bundle size is a
+// template parameter, so the loop over rhs unrolls and all of a link's loads
+// are in flight together.  Results go through LDS and are written as four
+// contiguous stretches of the output ([4][V][3][3], one per direction), 16
+// bytes per lane per store.
+template <int NRHS>
+__global__ __launch_bounds__(kForceBlock) void k_force(Lat lat, const d2* __restrict__ xc,
+                                                       const d2* __restrict__ yc,
+                                                       const d2* __restrict__ txc,
+                                                       const d2* __restrict__ syc,
+                                                       d2* __restrict__ GU, d2* __restrict__ GN)
 {
+    __shared__ d2 sg[kForceBlock * 9];
     const int V = 2 * lat.Vh;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 4 * V) return;
-    const int mu = idx / V;
-    const int a = idx - mu * V;
+    const int a0 = blockIdx.x * kForceSites;
+    const int nsites = min(kForceSites, V - a0);
+    const int mu = threadIdx.x / kForceSites;
+    const int al = threadIdx.x - mu * kForceSites;
+    const bool live = al < nsites;
+    const int a = live ? a0 + al : a0;
     int c[4];
     int r = a;
     for (int nu = 0; nu < 4; ++nu) {
@@ -34,44 +52,76 @@ __global__ void k_force(Lat lat, int nrhs, const d2* __restrict__ x, const d2* _
         r /= lat.L[nu];
     }
     const int par = (c[0] + c[1] + c[2] + c[3]) & 1;
-    const size_t ia = (size_t)(a >> 1) * 3 * nrhs;
+    const size_t cs = (size_t)lat.Vh * NRHS;  // colour stride
+    const size_t ia = (size_t)(a >> 1) * NRHS;
+    // even root: (u1, v1, u2, v2) = (y_a, t_b, x_a, s_b); odd: (t_a, y_b, s_a, x_b)
+    const d2* u1 = par == 0 ? yc : txc;
+    const d2* v1 = par == 0 ? txc : yc;
+    const d2* u2 = par == 0 ? xc : syc;
+    const d2* v2 = par == 0 ? syc : xc;
+    const double sign = par == 0 ? 1.0 : -1.0;
     for (int pass = 0; pass < 2; ++pass) {
         const int h = pass == 0 ? 1 : 3;
         int d[4] = {c[0], c[1], c[2], c[3]};
         d[mu] = (d[mu] + h) % lat.L[mu];
         const int b = d[0] + lat.L[0] * (d[1] + lat.L[1] * (d[2] + lat.L[2] * d[3]));
-        const size_t ib = (size_t)(b >> 1) * 3 * nrhs;
-        // even root: (u1, v1, u2, v2) = (y_a, t_b, x_a, s_b); odd: (t_a, y_b, s_a, x_b)
-        const d2* u1 = par == 0 ? y : tx;
-        const d2* v1 = par == 0 ? tx : y;
-        const d2* u2 = par == 0 ? x : sy;
-        const d2* v2 = par == 0 ? sy : x;
-        const double sign = par == 0 ? 1.0 : -1.0;
+        const size_t ib = (size_t)(b >> 1) * NRHS;
         d2 G[9];
+#pragma unroll
         for (int e = 0; e < 9; ++e) G[e] = d2{0, 0};
-        for (int k = 0; k < nrhs; ++k) {
-            d2 a1[3], b1[3], a2[3], b2[3];
-            for (int cc = 0; cc < 3; ++cc) {
-                a1[cc] = u1[ia + cc * nrhs + k];
-                b1[cc] = v1[ib + cc * nrhs + k];
-                a2[cc] = u2[ia + cc * nrhs + k];
-                b2[cc] = v2[ib + cc * nrhs + k];
+        if (live) {
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) {
+                d2 a1[3], b1[3], a2[3], b2[3];
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) {
+                    a1[cc] = u1[cc * cs + ia + k];
+                    b1[cc] = v1[cc * cs + ib + k];
+                    a2[cc] = u2[cc * cs + ia + k];
+                    b2[cc] = v2[cc * cs + ib + k];
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        G[3 * i + j] += cmul_conj(a1[i], b1[j]) + cmul_conj(a2[i], b2[j]);
             }
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) G[3 * i + j] += cmul_conj(a1[i], b1[j]) + cmul_conj(a2[i], b2[j]);
         }
-        d2* out = (pass == 0 ? GU : GN) + ((size_t)mu * V + a) * 9;
-        for (int e = 0; e < 9; ++e) out[e] = d2{sign * G[e].x, sign * G[e].y};
+        __syncthreads();  // the previous pass's stores have read sg
+#pragma unroll
+        for (int e = 0; e < 9; ++e) sg[threadIdx.x * 9 + e] = d2{sign * G[e].x, sign * G[e].y};
+        __syncthreads();
+        d2* out = pass == 0 ? GU : GN;
+        // sg holds [mu][site][9]; direction m's links are out[(m V + a0) * 9 ...]
+        for (int q = threadIdx.x; q < kForceBlock * 9; q += kForceBlock) {
+            const int m = q / (kForceSites * 9), w = q - m * (kForceSites * 9);
+            if (w < nsites * 9) out[((size_t)m * V + a0) * 9 + w] = sg[q];
+        }
     }
 }
 
-hipError_t launch_force(const Lat& lat, int nrhs, const d2* x, const d2* y, const d2* tx,
-                        const d2* sy, d2* GU, d2* GN, hipStream_t s)
+hipError_t launch_force(const Lat& lat, int nrhs, const d2* xc, const d2* yc, const d2* txc,
+                        const d2* syc, d2* GU, d2* GN, hipStream_t s)
 {
-    const long n = 4L * 2 * lat.Vh;
-    const int bs = 128;
-    const int grid = (int)((n + bs - 1) / bs);
-    hipLaunchKernelGGL(k_force, dim3(grid), dim3(bs), 0, s, lat, nrhs, x, y, tx, sy, GU, GN);
+    const int V = 2 * lat.Vh;
+    const int grid = (V + kForceSites - 1) / kForceSites;
+    switch (nrhs) {
+#define HISQ_FORCE_CASE(N)                                                                         \
+    case N:                                                                                        \
+        hipLaunchKernelGGL(k_force<N>, dim3(grid), dim3(kForceBlock), 0, s, lat, xc, yc, txc, syc, GU, \
+                           GN);                                                                    \
+        break;
+        HISQ_FORCE_CASE(1)
+        HISQ_FORCE_CASE(2)
+        HISQ_FORCE_CASE(3)
+        HISQ_FORCE_CASE(4)
+        HISQ_FORCE_CASE(5)
+        HISQ_FORCE_CASE(6)
+        HISQ_FORCE_CASE(7)
+        HISQ_FORCE_CASE(8)
+#undef HISQ_FORCE_CASE
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -289,7 +289,8 @@ int report_error(int code, const char* fmt, ...);
 // Link packing (pack.hip) and the link force (force.hip).
 hipError_t launch_pack(const Lat& lat, const d2* U, const d2* N, int prec, int naik,
                        void* packed, hipStream_t s);
-hipError_t launch_force(const Lat& lat, int nrhs, const d2* x, const d2* y, const d2* tx,
-                        const d2* sy, d2* GU, d2* GN, hipStream_t s);
+// link force from colour-major FP64 fields x, y (even) and D_oe x, D_oe y (odd)
+hipError_t launch_force(const Lat& lat, int nrhs, const d2* xc, const d2* yc, const d2* txc,
+                        const d2* syc, d2* GU, d2* GN, hipStream_t s);
 
 }  // namespace hisq
