@@ -21,6 +21,23 @@ __device__ __forceinline__ d2 cmul_conj(d2 a, d2 b)  // a * conj(b)
 constexpr int kForceSites = 32;              // sites per work-group
 constexpr int kForceBlock = 4 * kForceSites;  // one thread per (direction, site)
 
+// Work-group -> block of kForceSites canonical sites.  Where the lattice allows
+// (L[2] a multiple of the 8 XCDs, whole blocks per (x, y) plane), XCD j (the
+// work-groups b with b mod 8 = j) owns z-planes [j zc, (j+1) zc) of every time
+// slice and walks them with the plane block outermost, then t, then z: the
+// neighbours of a link in x, y and t, and most in z, are fetched by the same
+// XCD shortly before or after, so they come from its L2.  Otherwise b itself.
+__device__ inline int force_block(int b, int nb, const Lat& lat)
+{
+    const int plane = lat.L[0] * lat.L[1];
+    if ((lat.L[2] & 7) || plane % kForceSites || nb != plane / kForceSites * lat.L[2] * lat.L[3])
+        return b;
+    const int zc = lat.L[2] >> 3, C = plane / kForceSites;
+    const int j = b & 7, m = b >> 3;
+    const int zl = m % zc, t = (m / zc) % lat.L[3], c = m / (zc * lat.L[3]);
+    return (t * lat.L[2] + j * zc + zl) * C + c;
+}
+
 // One thread per link (mu, a).  A work-group covers the links of all four
 // directions of kForceSites consecutive canonical sites (thread = mu * 32 +
 // site), so a site's own fields, read by its four links, come from the cache
@@ -39,7 +56,7 @@ __global__ __launch_bounds__(kForceBlock) void k_force(Lat lat, const d2* __rest
 {
     __shared__ d2 sg[kForceBlock * 9];
     const int V = 2 * lat.Vh;
-    const int a0 = blockIdx.x * kForceSites;
+    const int a0 = force_block(blockIdx.x, gridDim.x, lat) * kForceSites;
     const int nsites = min(kForceSites, V - a0);
     const int mu = threadIdx.x / kForceSites;
     const int al = threadIdx.x - mu * kForceSites;

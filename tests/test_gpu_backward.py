@@ -29,9 +29,11 @@ def _backward(H, L, U, N, m, x, phi, mode=0, naik=0, tol=1e-10):
     return host(gU), host(gN), float(gm.item()), host(gb)
 
 
-@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 6, 4)])
+@pytest.mark.parametrize("L", [(4, 4, 4, 4), (6, 4, 6, 4), (6, 6, 6, 6), (8, 8, 8, 4)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_force_matches_oracle(L, mode):
+    """6^4 leaves a ragged last work-group (1296 sites, 32 per group); 8^3 x 4
+    runs the XCD-ordered site blocks (z extent a multiple of 8)."""
     H = gpu_lib()
     m, n = 0.05, 3
     U, N = W.make_links(L, 0.3, 201)
