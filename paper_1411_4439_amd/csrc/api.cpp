@@ -680,8 +680,11 @@ struct Engine {
             iter_args<T>(q, bp.k1, bp.k2, bp.k3);
             bp.n = q.n;
             bp.nr = batched_nr_ok(q.n, q.bnr) ? q.bnr : q.n;
-            bp.k1.remap = bp.k2.remap = bp.k3.remap = 0;
-            const long threads = (long)q.lat.Vh * (q.n / bp.nr);
+            // XCD-owned z-chunks where the problem's tiles allow, else one
+            // contiguous slab per XCD
+            const int G = q.n / bp.nr;
+            bp.k1.remap = bp.k2.remap = bp.k3.remap = t_order_ok(q.lat, G, bs, 3) ? 3 : 1;
+            const long threads = (long)q.lat.Vh * G;
             bp.nblocks = (int)((threads + bs - 1) / bs);
             bp.k1.ntiles = bp.k2.ntiles = bp.k3.ntiles = bp.nblocks;
             bp.block_start = start;

@@ -80,19 +80,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_pupdate_batched(const BatchTable<
     const int bid = (int)blockIdx.x - bp.block_start;
     if (bid >= bp.nblocks) return;
     const int nb = bp.nblocks;
+    const int tile = tile_of_block(bid, nb, bp.k1.remap, bp.k1.lat, (int)blockDim.x / (bp.n / bp.nr));
     switch (bp.n * 16 + bp.nr) {
-    case 1 * 16 + 1: pupdate_tile<T, 1, 1>(bp.k1, bid, nb, bid); break;
-    case 2 * 16 + 2: pupdate_tile<T, 2, 2>(bp.k1, bid, nb, bid); break;
-    case 2 * 16 + 1: pupdate_tile<T, 2, 1>(bp.k1, bid, nb, bid); break;
-    case 3 * 16 + 3: pupdate_tile<T, 3, 3>(bp.k1, bid, nb, bid); break;
-    case 4 * 16 + 4: pupdate_tile<T, 4, 4>(bp.k1, bid, nb, bid); break;
-    case 4 * 16 + 2: pupdate_tile<T, 4, 2>(bp.k1, bid, nb, bid); break;
-    case 5 * 16 + 5: pupdate_tile<T, 5, 5>(bp.k1, bid, nb, bid); break;
-    case 6 * 16 + 6: pupdate_tile<T, 6, 6>(bp.k1, bid, nb, bid); break;
-    case 6 * 16 + 3: pupdate_tile<T, 6, 3>(bp.k1, bid, nb, bid); break;
-    case 7 * 16 + 7: pupdate_tile<T, 7, 7>(bp.k1, bid, nb, bid); break;
-    case 8 * 16 + 8: pupdate_tile<T, 8, 8>(bp.k1, bid, nb, bid); break;
-    case 8 * 16 + 4: pupdate_tile<T, 8, 4>(bp.k1, bid, nb, bid); break;
+    case 1 * 16 + 1: pupdate_tile<T, 1, 1>(bp.k1, tile, nb, bid); break;
+    case 2 * 16 + 2: pupdate_tile<T, 2, 2>(bp.k1, tile, nb, bid); break;
+    case 2 * 16 + 1: pupdate_tile<T, 2, 1>(bp.k1, tile, nb, bid); break;
+    case 3 * 16 + 3: pupdate_tile<T, 3, 3>(bp.k1, tile, nb, bid); break;
+    case 4 * 16 + 4: pupdate_tile<T, 4, 4>(bp.k1, tile, nb, bid); break;
+    case 4 * 16 + 2: pupdate_tile<T, 4, 2>(bp.k1, tile, nb, bid); break;
+    case 5 * 16 + 5: pupdate_tile<T, 5, 5>(bp.k1, tile, nb, bid); break;
+    case 6 * 16 + 6: pupdate_tile<T, 6, 6>(bp.k1, tile, nb, bid); break;
+    case 6 * 16 + 3: pupdate_tile<T, 6, 3>(bp.k1, tile, nb, bid); break;
+    case 7 * 16 + 7: pupdate_tile<T, 7, 7>(bp.k1, tile, nb, bid); break;
+    case 8 * 16 + 8: pupdate_tile<T, 8, 8>(bp.k1, tile, nb, bid); break;
+    case 8 * 16 + 4: pupdate_tile<T, 8, 4>(bp.k1, tile, nb, bid); break;
     default: break;
     }
 }

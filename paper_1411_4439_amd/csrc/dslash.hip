@@ -600,19 +600,22 @@ __global__ __launch_bounds__(kMaxBlock) void k_dslash_batched(const BatchTable<T
     if (bid >= bp.nblocks) return;
     const DslashArgs<T>& a = EPI == EPI_NORM ? bp.k2 : bp.k3;
     const int nb = bp.nblocks;
+    // the problem's tile order, on its own block range (the blocks with equal
+    // bid mod 8 still share one XCD)
+    const int tile = tile_of_block(bid, nb, a.remap, a.lat, (int)blockDim.x / (bp.n / bp.nr));
     switch (bp.n * 16 + bp.nr) {
-    case 1 * 16 + 1: dslash_tile<T, 1, 1, NK, EPI, true>(a, bid, nb, bid); break;
-    case 2 * 16 + 2: dslash_tile<T, 2, 2, NK, EPI, true>(a, bid, nb, bid); break;
-    case 2 * 16 + 1: dslash_tile<T, 2, 1, NK, EPI, true>(a, bid, nb, bid); break;
-    case 3 * 16 + 3: dslash_tile<T, 3, 3, NK, EPI, true>(a, bid, nb, bid); break;
-    case 4 * 16 + 4: dslash_tile<T, 4, 4, NK, EPI, true>(a, bid, nb, bid); break;
-    case 4 * 16 + 2: dslash_tile<T, 4, 2, NK, EPI, true>(a, bid, nb, bid); break;
-    case 5 * 16 + 5: dslash_tile<T, 5, 5, NK, EPI, true>(a, bid, nb, bid); break;
-    case 6 * 16 + 6: dslash_tile<T, 6, 6, NK, EPI, true>(a, bid, nb, bid); break;
-    case 6 * 16 + 3: dslash_tile<T, 6, 3, NK, EPI, true>(a, bid, nb, bid); break;
-    case 7 * 16 + 7: dslash_tile<T, 7, 7, NK, EPI, true>(a, bid, nb, bid); break;
-    case 8 * 16 + 8: dslash_tile<T, 8, 8, NK, EPI, true>(a, bid, nb, bid); break;
-    case 8 * 16 + 4: dslash_tile<T, 8, 4, NK, EPI, true>(a, bid, nb, bid); break;
+    case 1 * 16 + 1: dslash_tile<T, 1, 1, NK, EPI, true>(a, tile, nb, bid); break;
+    case 2 * 16 + 2: dslash_tile<T, 2, 2, NK, EPI, true>(a, tile, nb, bid); break;
+    case 2 * 16 + 1: dslash_tile<T, 2, 1, NK, EPI, true>(a, tile, nb, bid); break;
+    case 3 * 16 + 3: dslash_tile<T, 3, 3, NK, EPI, true>(a, tile, nb, bid); break;
+    case 4 * 16 + 4: dslash_tile<T, 4, 4, NK, EPI, true>(a, tile, nb, bid); break;
+    case 4 * 16 + 2: dslash_tile<T, 4, 2, NK, EPI, true>(a, tile, nb, bid); break;
+    case 5 * 16 + 5: dslash_tile<T, 5, 5, NK, EPI, true>(a, tile, nb, bid); break;
+    case 6 * 16 + 6: dslash_tile<T, 6, 6, NK, EPI, true>(a, tile, nb, bid); break;
+    case 6 * 16 + 3: dslash_tile<T, 6, 3, NK, EPI, true>(a, tile, nb, bid); break;
+    case 7 * 16 + 7: dslash_tile<T, 7, 7, NK, EPI, true>(a, tile, nb, bid); break;
+    case 8 * 16 + 8: dslash_tile<T, 8, 8, NK, EPI, true>(a, tile, nb, bid); break;
+    case 8 * 16 + 4: dslash_tile<T, 8, 4, NK, EPI, true>(a, tile, nb, bid); break;
     default: break;
     }
 }

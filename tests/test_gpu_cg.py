@@ -196,6 +196,46 @@ def test_batched_equals_separate_solves():
             assert rel_l2_per_rhs(xh, host(refs[j])) <= 1e-7
 
 
+@pytest.mark.parametrize("specs", [
+    [((8, 8, 8, 4), 3, 0.05), ((4, 4, 4, 4), 1, 0.1)],           # 3 and 1 rhs per thread
+    [((6, 6, 6, 4), 5, 0.01), ((8, 8, 8, 4), 3, 0.05)],           # 5 rhs per thread
+    [((8, 8, 4, 4), 8, 0.05), ((6, 6, 6, 4), 5, 0.01)],           # 8 rhs per thread
+])
+def test_batched_builtin_tiles(specs):
+    """Batches on the built-in tiles (every problem n rhs per thread, 128
+    threads): 3 and 1, 5 and 3, 8 and 5 rhs per thread side by side, the
+    lattices with z extent 8 on the XCD-ordered tile walk; each problem agrees
+    with its own solve and reaches the oracle's residual."""
+    H = gpu_lib()
+    import torch
+    H.hisq_set_tuning(2)
+    try:
+        probs, keep, refs = [], [], []
+        for j, (L, n, m) in enumerate(specs):
+            U, N = W.make_links(L, 0.3, 300 + j)
+            links = H.Links(L, dev(U), dev(N), f32=False, r14=True)
+            b = W.make_sources(L, n, 310 + j)
+            bd = dev(b)
+            x = torch.empty_like(bd)
+            keep.append((U, N, b, x))
+            probs.append(H.Problem(H.geom(L), m, n, links.f64.data_ptr(), links.f32r14.data_ptr(),
+                                   bd.data_ptr(), x.data_ptr()))
+            refs.append((links, bd, H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14)[0]))
+        p = H.hisq_default_params(mode=H.MODE_MIXED, naik=H.NAIK_R14)
+        ws = H.empty_bytes(H.hisq_batched_workspace_bytes(probs, H.MODE_MIXED))
+        status, infos = H.hisq_cg_solve_batched(probs, p, ws)
+        assert status == H.HISQ_OK
+        for j, (L, n, m) in enumerate(specs):
+            U, N, b, x = keep[j]
+            xh = host(x)
+            res = oracle.residual(L, U, N, m, b, xh)
+            say("class batch", L, n, infos[j].iters[:n], res.max())
+            assert res.max() <= 1e-10
+            assert rel_l2_per_rhs(xh, host(refs[j][2])) <= 1e-7
+    finally:
+        H.hisq_set_tuning(0)
+
+
 def test_headline_mixed_8rhs_true_residual():
     """48^3 x 12, m = 0.01, eps = 0.2, 8 rhs, mixed precision with r14 Naik
     links: the oracle's FP64 true residual of the returned x is <= 1e-10."""
