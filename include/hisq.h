@@ -40,8 +40,10 @@
  *            hisq_info / hisq_params / hisq_problem structs, which are host memory.
  *            Field, link and workspace buffers must be 16-byte aligned (they are
  *            read with 16-byte vector loads); HISQ_EINVAL otherwise.
- *            The library allocates no device memory; solvers take a workspace
- *            sized by hisq_workspace_bytes().  Buffers must not overlap.
+ *            No entry point allocates device memory: the solvers take a
+ *            workspace sized by the *_workspace_bytes() queries
+ *            (hisq_cg_solve_noalloc uses a static device array instead).
+ *            Buffers must not overlap.
  * Streams    `stream` is a hipStream_t passed as void* (NULL = default stream).
  *            hisq_dslash and hisq_pack_links (FULL Naik) are asynchronous.  The
  *            solvers block the calling host thread until the solve ends, because
