@@ -15,7 +15,9 @@ The JSON line reports
                  (links + one read of the input + one write/update of outputs),
   roofline       the dominant kernel's achieved GB/s against 8 TB/s,
   cg             time-to-solution of the step against 8 sequential FP64 1-rhs
-                 solves of the same sources (same GPU), iterations, residuals,
+                 solves of the same sources (same GPU), iterations, residuals;
+                 bundle_forms: the same 8-rhs solve in FP64 and in mixed
+                 precision with full, r13 and r9 Naik links,
   accuracy       per-rhs true residual and the a-posteriori solution-error bound,
   dslash_sweep   standalone Dslash GB/s for n = 1, 2, 4, 8 (FP64, FP32, r14, r13, r9),
   full_and_trace the full-matrix solve and one bundle of eq. (2) trace terms,
@@ -515,6 +517,30 @@ def main():
         result["cg"]["fp64_iters"] = it64
         result["cg"]["speedup_vs_fp64_1rhs"] = round(fp64_s / (ms_per_step / 1e3), 2)
         log("FP64 %d x 1-rhs: %.3f s (iters %s)" % (n, fp64_s, it64))
+
+        # the same bundle in the other precision forms: FP64 throughout, and
+        # mixed with the Naik links stored in full (18 reals), r13 and r9
+        # (autotuned tiles, poll blocks as hipGraphs; one tuning + warm-up solve,
+        # then one timed)
+        forms = {}
+        wsf = H.empty_bytes(H.hisq_workspace_bytes(L, n, H.MODE_FP64))
+        for tag, mode, nk2 in (("fp64", H.MODE_FP64, H.NAIK_FULL), ("mixed_full", H.MODE_MIXED, H.NAIK_FULL),
+                               ("mixed_r13", H.MODE_MIXED, H.NAIK_R13), ("mixed_r9", H.MODE_MIXED, H.NAIK_R9)):
+            l32 = links.packed(H.PREC_F32, nk2) if mode == H.MODE_MIXED else None
+            if mode == H.MODE_MIXED and l32 is None:
+                continue
+            wsb = wsf if mode == H.MODE_FP64 else ws
+            p = H.hisq_default_params(mode=mode, naik=nk2, tol=1e-10)
+            H.hisq_cg_solve(L, m, n, p, links.f64, l32, bd, x, wsb)
+            torch.cuda.synchronize()
+            tf = time.perf_counter()
+            st, info = H.hisq_cg_solve(L, m, n, p, links.f64, l32, bd, x, wsb)
+            torch.cuda.synchronize()
+            forms[tag] = {"seconds": round(time.perf_counter() - tf, 4), "status": st,
+                          "iters_max": max(info.iters[:n]), "reliable_updates": info.reliable_updates,
+                          "rel_true_res_max": float("%.3e" % max(info.rel_true_res[:n]))}
+        result["cg"]["bundle_forms"] = forms
+        log("bundle forms", json.dumps(forms))
 
     if not args.no_sweep:
         sweep = {}
