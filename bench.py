@@ -22,6 +22,8 @@ The JSON line reports
   dslash_sweep   standalone Dslash GB/s for n = 1, 2, 4, 8 (FP64, FP32, r14, r13, r9),
   full_and_trace the full-matrix solve and one bundle of eq. (2) trace terms,
   config2        32^3 x 8: Dslash sweep and CG time against bundle size,
+  paper_lattice  64^3 x 16 (the paper's production size): r14 Dslash sweep and
+                 one 8-rhs mixed solve,
   backward       24^3 x 6 gradient: adjoint solve and link-force kernel,
   batched        six solves in one launch per CG phase against six separate ones,
   cpu_baseline   the FP64 CPU oracle on the host cores: Dslash rates, full CGs,
@@ -63,9 +65,12 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-paper-lattice", action="store_true",
+                    help="skip the 64^3 x 16 Dslash sweep and solve")
     ap.add_argument("--no-trace", action="store_true")
     ap.add_argument("--no-config2", action="store_true",
-                    help="skip the 32^3 x 8 Dslash sweep and CG bundle gains")
+                    help="skip the 32^3 x 8 Dslash sweep and CG bundle gains (and the "
+                         "64^3 x 16 block)")
     ap.add_argument("--no-backward", action="store_true",
                     help="skip the 24^3 x 6 gradient (adjoint solve + link force) timing")
     ap.add_argument("--no-oracle-cg", action="store_true",
@@ -206,6 +211,47 @@ def config2_block(H, R, W, dev, stream):
     cg["paper_4rhs_gain"] = "about 2.05 (95% of the 2.16 Dslash intensity gain), Sec. 3, single precision"
     return {"workload": "32x32x32x8, m=0.02, eps=0.3, colour-major fields, autotuned tiles",
             "dslash_sweep": sweep, "cg": cg}
+
+
+def paper_lattice_block(H, R, W, dev, stream):
+    """64^3 x 16, the size of the paper's production lattices (Sec. 3): the
+    standalone FP32 r14 half-Dslash at n = 1, 2, 4, 8 (colour-major, autotuned)
+    and one mixed-precision r14 CG solve of an 8-rhs bundle (m = 0.01, eps =
+    0.2, true residual 1e-10), to show how the kernels scale past the headline
+    lattice."""
+    import torch
+    L, m, n = (64, 64, 64, 16), 0.01, 8
+    Vh = W.half_volume(L)
+    t0 = time.time()
+    U, N = W.make_links(L, 0.2, W.links_seed(6))  # not cached: 4.8 GB on the host
+    b = W.make_sources(L, n, W.sources_seed(6))
+    log("64^3 x 16 inputs in %.1f s" % (time.time() - t0))
+    links = H.Links(L, dev(U), dev(N), f32=False, r14=True)
+    del U, N
+    H.hisq_set_tuning(0)
+    bd = dev(b)
+    sweep = {}
+    packed = links.packed(H.PREC_F32, H.NAIK_R14)
+    for nn in (1, 2, 4, 8):
+        vin = bd[:, :, :nn].to(torch.complex64).permute(1, 0, 2).contiguous()
+        vout = torch.empty_like(vin)
+        ms = median_event_ms(lambda: H.hisq_dslash(L, 1, nn, H.PREC_F32, H.NAIK_R14, H.LAYOUT_COLOUR,
+                                                   packed, vin, vout), stream, 100, warm=10)
+        byt = Vh * (R.LINK_BYTES_F32["r14"] + 2 * R.VEC_BYTES_F32 * nn)
+        sweep["f32_r14_n%d" % nn] = {"ms": round(ms, 4), "GBps": round(byt / ms / 1e6, 1),
+                                     "pct_hbm_peak": round(byt / ms / 1e6 / HBM_PEAK_GBPS * 100, 1)}
+        del vin, vout
+    ws = H.empty_bytes(H.hisq_workspace_bytes(L, n, H.MODE_MIXED))
+    H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14, ws=ws)  # tune + warm
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st, info = H.solve(links, m, bd, mode=H.MODE_MIXED, naik=H.NAIK_R14, ws=ws)
+    torch.cuda.synchronize()
+    cg = {"seconds": round(time.perf_counter() - t1, 4), "status": st, "iters_max": max(info["iters"]),
+          "reliable_updates": info["reliable_updates"],
+          "rel_true_res_max": float("%.3e" % max(info["rel_true_res"]))}
+    return {"workload": "64x64x64x16, m=0.01, eps=0.2, 8 rhs, colour-major fields, autotuned tiles",
+            "dslash_sweep": sweep, "cg_mixed_r14_n8": cg}
 
 
 def backward_block(H, W, dev):
@@ -646,6 +692,9 @@ def main():
 
     if not args.no_config2:
         result["config2"] = config2_block(H, R, W, dev, stream)
+    if not args.no_config2 and not args.no_paper_lattice:
+        result["paper_lattice"] = paper_lattice_block(H, R, W, dev, stream)
+        log("paper lattice", json.dumps(result["paper_lattice"]))
         log("config2", json.dumps(result["config2"]))
 
     if not args.no_backward:
