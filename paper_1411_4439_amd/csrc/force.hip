@@ -18,8 +18,9 @@ __device__ __forceinline__ d2 cmul_conj(d2 a, d2 b)  // a * conj(b)
     return d2{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-constexpr int kForceSites = 32;              // sites per work-group
-constexpr int kForceBlock = 4 * kForceSites;  // one thread per (direction, site)
+constexpr int kForceSites = 32;                   // sites per work-group
+constexpr int kForceLinks = 4 * kForceSites;      // links (direction, site) per work-group
+constexpr int kForceBlock = 2 * kForceLinks;      // two threads per link, one per term
 
 // Work-group -> block of kForceSites canonical sites.  Where the lattice allows
 // (L[2] a multiple of the 8 XCDs, whole blocks per (x, y) plane), XCD j (the
@@ -38,15 +39,19 @@ __device__ inline int force_block(int b, int nb, const Lat& lat)
     return (t * lat.L[2] + j * zc + zl) * C + c;
 }
 
-// One thread per link (mu, a).  A work-group covers the links of all four
-// directions of kForceSites consecutive canonical sites (thread = mu * 32 +
-// site), so a site's own fields, read by its four links, come from the cache
-// after the first.  Fields are colour-major, [3][Vh][n]: the rhs of one
-// colour of a site are n consecutive complex numbers; the bundle size is a
-// template parameter, so the loop over rhs unrolls and all of a link's loads
-// are in flight together.  Results go through LDS and are written as four
-// contiguous stretches of the output ([4][V][3][3], one per direction), 16
-// bytes per lane per store.
+// Two threads per link (mu, a), one per term of the sum over the bundle
+// (thread = term * 128 + mu * 32 + site): term 0 accumulates u1 v1^dag, term 1
+// u2 v2^dag, so each thread holds half the loads of a link, which keeps the
+// register count (and so the waves resident per SIMD) at about half of what
+// one thread per link needs.  A work-group covers the links of all four
+// directions of kForceSites consecutive canonical sites, so a site's own
+// fields, read by its four links, come from the cache after the first.
+// Fields are colour-major, [3][Vh][n]: the rhs of one colour of a site are n
+// consecutive complex numbers; the bundle size is a template parameter, so
+// the loop over rhs unrolls and all of a term's loads are in flight together.
+// The two terms meet in LDS and the sums are written as four contiguous
+// stretches of the output ([4][V][3][3], one per direction), 16 bytes per
+// lane per store.
 template <int NRHS>
 __global__ __launch_bounds__(kForceBlock) void k_force(Lat lat, const d2* __restrict__ xc,
                                                        const d2* __restrict__ yc,
@@ -54,12 +59,14 @@ __global__ __launch_bounds__(kForceBlock) void k_force(Lat lat, const d2* __rest
                                                        const d2* __restrict__ syc,
                                                        d2* __restrict__ GU, d2* __restrict__ GN)
 {
-    __shared__ d2 sg[kForceBlock * 9];
+    __shared__ d2 sg[2][kForceLinks * 9];
     const int V = 2 * lat.Vh;
     const int a0 = force_block(blockIdx.x, gridDim.x, lat) * kForceSites;
     const int nsites = min(kForceSites, V - a0);
-    const int mu = threadIdx.x / kForceSites;
-    const int al = threadIdx.x - mu * kForceSites;
+    const int term = threadIdx.x / kForceLinks;
+    const int link = threadIdx.x - term * kForceLinks;
+    const int mu = link / kForceSites;
+    const int al = link - mu * kForceSites;
     const bool live = al < nsites;
     const int a = live ? a0 + al : a0;
     int c[4];
@@ -71,11 +78,10 @@ __global__ __launch_bounds__(kForceBlock) void k_force(Lat lat, const d2* __rest
     const int par = (c[0] + c[1] + c[2] + c[3]) & 1;
     const size_t cs = (size_t)lat.Vh * NRHS;  // colour stride
     const size_t ia = (size_t)(a >> 1) * NRHS;
-    // even root: (u1, v1, u2, v2) = (y_a, t_b, x_a, s_b); odd: (t_a, y_b, s_a, x_b)
-    const d2* u1 = par == 0 ? yc : txc;
-    const d2* v1 = par == 0 ? txc : yc;
-    const d2* u2 = par == 0 ? xc : syc;
-    const d2* v2 = par == 0 ? syc : xc;
+    // even root: term 0 (u, v) = (y_a, t_b), term 1 (x_a, s_b);
+    // odd root:  term 0 (t_a, y_b), term 1 (s_a, x_b)
+    const d2* u = par == 0 ? (term == 0 ? yc : xc) : (term == 0 ? txc : syc);
+    const d2* v = par == 0 ? (term == 0 ? txc : syc) : (term == 0 ? yc : xc);
     const double sign = par == 0 ? 1.0 : -1.0;
     for (int pass = 0; pass < 2; ++pass) {
         const int h = pass == 0 ? 1 : 3;
@@ -89,30 +95,30 @@ __global__ __launch_bounds__(kForceBlock) void k_force(Lat lat, const d2* __rest
         if (live) {
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) {
-                d2 a1[3], b1[3], a2[3], b2[3];
+                d2 ua[3], vb[3];
 #pragma unroll
                 for (int cc = 0; cc < 3; ++cc) {
-                    a1[cc] = u1[cc * cs + ia + k];
-                    b1[cc] = v1[cc * cs + ib + k];
-                    a2[cc] = u2[cc * cs + ia + k];
-                    b2[cc] = v2[cc * cs + ib + k];
+                    ua[cc] = u[cc * cs + ia + k];
+                    vb[cc] = v[cc * cs + ib + k];
                 }
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        G[3 * i + j] += cmul_conj(a1[i], b1[j]) + cmul_conj(a2[i], b2[j]);
+                    for (int j = 0; j < 3; ++j) G[3 * i + j] += cmul_conj(ua[i], vb[j]);
             }
         }
         __syncthreads();  // the previous pass's stores have read sg
 #pragma unroll
-        for (int e = 0; e < 9; ++e) sg[threadIdx.x * 9 + e] = d2{sign * G[e].x, sign * G[e].y};
+        for (int e = 0; e < 9; ++e) sg[term][link * 9 + e] = d2{sign * G[e].x, sign * G[e].y};
         __syncthreads();
         d2* out = pass == 0 ? GU : GN;
-        // sg holds [mu][site][9]; direction m's links are out[(m V + a0) * 9 ...]
-        for (int q = threadIdx.x; q < kForceBlock * 9; q += kForceBlock) {
+        // sg[.] holds [mu][site][9]; direction m's links are out[(m V + a0) * 9 ...]
+        for (int q = threadIdx.x; q < kForceLinks * 9; q += kForceBlock) {
             const int m = q / (kForceSites * 9), w = q - m * (kForceSites * 9);
-            if (w < nsites * 9) out[((size_t)m * V + a0) * 9 + w] = sg[q];
+            if (w < nsites * 9) {
+                const d2 g0 = sg[0][q], g1 = sg[1][q];
+                out[((size_t)m * V + a0) * 9 + w] = d2{g0.x + g1.x, g0.y + g1.y};
+            }
         }
     }
 }
