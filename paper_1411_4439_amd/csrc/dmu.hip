@@ -4,7 +4,9 @@
 // the hop by h^n and every spatial hop drops out.  So d^n D / d mu^n is the
 // Dslash restricted to the four temporal slots (+1, -1, +3, -3), weighted by
 // 1, (-1)^n, 3^n, (-3)^n.  FP64 links, site-major fields [Vh][3][n]; one thread
-// per output site and all rhs.  Off the CG's hot path: the estimator spends
+// per output site and rhs, so the n threads of a site are adjacent lanes that
+// read n consecutive complex numbers per colour (one contiguous stretch) and
+// the same link (one request).  Off the CG's hot path: the estimator spends
 // its time in the solves.
 #include "stencil.h"
 
@@ -15,29 +17,25 @@ __global__ __launch_bounds__(256) void k_dslash_dmu(Lat lat, int parity, const d
                                                     const d2* __restrict__ in, d2* __restrict__ out,
                                                     double wp1, double wm1, double wp3, double wm3)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / NRHS), k = (int)(t - (long)i * NRHS);
     if (i >= lat.Vh) return;
     const SiteCoord sc = site_coord(lat, parity, i);
-    d2 acc[3][NRHS];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int k = 0; k < NRHS; ++k) acc[a][k] = d2{0.0, 0.0};
+    d2 acc[3] = {d2{0.0, 0.0}, d2{0.0, 0.0}, d2{0.0, 0.0}};
     auto slot = [&](auto S, double w) {
         constexpr int s = decltype(S)::value;
         d2 m[9];
         load_link<double, HISQ_NAIK_FULL, s>(lk, lat.Vh, i, m);
         const int nb = neighbour<s>(lat, sc);
+        d2 v[3];
 #pragma unroll
-        for (int e = 0; e < 9; ++e) m[e] = d2{w * m[e].x, w * m[e].y};
+        for (int b = 0; b < 3; ++b) v[b] = in[((size_t)nb * 3 + b) * NRHS + k];
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+        for (int b = 0; b < 3; ++b) {
+            const d2 wv = d2{w * v[b].x, w * v[b].y};
 #pragma unroll
-            for (int k = 0; k < NRHS; ++k) {
-                const d2 v = in[((size_t)nb * 3 + b) * NRHS + k];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) cfma(acc[a][k], m[3 * a + b], v);
-            }
+            for (int a = 0; a < 3; ++a) cfma(acc[a], m[3 * a + b], wv);
+        }
     };
     // slot s = 4 * hop + mu; the packed backward slots already carry the minus
     // sign of eq. (3)
@@ -46,9 +44,7 @@ __global__ __launch_bounds__(256) void k_dslash_dmu(Lat lat, int parity, const d
     slot(std::integral_constant<int, 11>{}, wp3);
     slot(std::integral_constant<int, 15>{}, wm3);
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int k = 0; k < NRHS; ++k) out[((size_t)i * 3 + a) * NRHS + k] = acc[a][k];
+    for (int a = 0; a < 3; ++a) out[((size_t)i * 3 + a) * NRHS + k] = acc[a];
 }
 
 hipError_t launch_dslash_dmu(const Lat& lat, int parity, int nrhs, int nder, const d2* lk,
@@ -60,7 +56,8 @@ hipError_t launch_dslash_dmu(const Lat& lat, int parity, int nrhs, int nder, con
         return w;
     };
     const double wp1 = pw(1, nder), wm1 = pw(-1, nder), wp3 = pw(3, nder), wm3 = pw(-3, nder);
-    const dim3 grid((lat.Vh + 127) / 128), block(128);
+    const long threads = (long)lat.Vh * nrhs;
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
     switch (nrhs) {
 #define HISQ_DMU_CASE(N)                                                                          \
     case N:                                                                                       \
