@@ -47,6 +47,27 @@ int fail(int code, const char* fmt, ...)
         if (e_ != hipSuccess) return fail(HISQ_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Runs f when the scope ends, also on an early error return: releases HIP
+// events and graphs on every path.
+template <typename F>
+struct ScopeExit {
+    F f;
+    ~ScopeExit() { f(); }
+};
+template <typename F>
+ScopeExit<F> on_scope_exit(F f)
+{
+    return ScopeExit<F>{f};
+}
+void destroy_events(hipEvent_t* e, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        if (e[i]) {
+            hipEventDestroy(e[i]);
+            e[i] = nullptr;
+        }
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 int check_geom(const hisq_geom* g, Lat* lat)
@@ -403,9 +424,11 @@ int get_tile(const Lat& lat, int n, int prec, int nk, const DslashArgs<T>& probe
             return HISQ_OK;
         }
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    auto release = on_scope_exit([&] { destroy_events(tev, 2); });
+    HIP_TRY(hipEventCreate(&tev[0]));
+    HIP_TRY(hipEventCreate(&tev[1]));
+    hipEvent_t e0 = tev[0], e1 = tev[1];
     Tile best = default_tile(n, prec);
     float best_ms = 1e30f;
     // candidates: unstaged tiles of 64, 128, 256 threads, then (colour-major
@@ -439,8 +462,6 @@ int get_tile(const Lat& lat, int n, int prec, int nk, const DslashArgs<T>& probe
                 }
             }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune_cache[key] = best;
@@ -758,9 +779,11 @@ int Engine::batched_time(void* host_buf, const std::vector<int>& which, int bs, 
 {
     int rc = mixed ? upload_table<float>(host_buf, which, bs) : upload_table<double>(host_buf, which, bs);
     if (rc) return rc;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    auto release = on_scope_exit([&] { destroy_events(tev, 2); });
+    HIP_TRY(hipEventCreate(&tev[0]));
+    HIP_TRY(hipEventCreate(&tev[1]));
+    hipEvent_t e0 = tev[0], e1 = tev[1];
     auto pair = [&]() -> int {
         if (mixed) {
             const auto* tab = reinterpret_cast<const BatchTable<float>*>(table);
@@ -782,8 +805,6 @@ int Engine::batched_time(void* host_buf, const std::vector<int>& which, int bs, 
     HIP_TRY(hipEventSynchronize(e1));
     float t = 0;
     HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     *ms = t / kReps;
     return HISQ_OK;
 }
@@ -956,12 +977,14 @@ int Engine::poll_and_update(CgState* host)
     }
     if (!any) return HISQ_OK;
     if ((rc = write_states(host))) return rc;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    auto release = on_scope_exit([&] { destroy_events(tev, 2); });
     if (prm.profile) {
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
-        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(hipEventCreate(&tev[0]));
+        HIP_TRY(hipEventCreate(&tev[1]));
+        HIP_TRY(hipEventRecord(tev[0], s));
     }
+    hipEvent_t e0 = tev[0], e1 = tev[1];
     for (Prob& q : P) {
         bool any_q = false;
         for (int k = 0; k < q.n; ++k) any_q = any_q || q.hs->sel[k];
@@ -978,8 +1001,6 @@ int Engine::poll_and_update(CgState* host)
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         kms[HISQ_K_RELIABLE] += ms;
         klaunch[HISQ_K_RELIABLE] += 1;
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
     }
     for (Prob& q : P) {
         CgState* h = q.hs;
@@ -1147,12 +1168,18 @@ int Engine::run(hisq_info* infos)
 
     const int kblk = poll_block_size();
     const bool profile = prm.profile != 0;
-    if (profile) {
-        ev.resize(4 * kblk);
-        for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    auto release = on_scope_exit([&] {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        destroy_events(ev.data(), ev.size());
+        ev.clear();
+    });
+    if (profile) {
+        ev.assign(4 * kblk, nullptr);
+        for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    }
     // Event timestamps are not available for events recorded inside a graph, so
     // a profiled solve launches its kernels directly on the stream.
     if (prm.use_graph && !profile) {
@@ -1182,10 +1209,6 @@ int Engine::run(hisq_info* infos)
         if (profile && (rc = collect_events(kblk))) return rc;
         if ((rc = poll_and_update(host))) return rc;
     }
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
-    for (auto& e : ev) hipEventDestroy(e);
-    ev.clear();
     const double secs =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     return finish(host, infos, secs);
@@ -1645,6 +1668,7 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     a.out = w.sy;
     HIP_TRY(launch_ds(EPI_PLAIN, nrhs, HISQ_NAIK_FULL, t, a, s, true));
     hipEvent_t fe[2] = {nullptr, nullptr};
+    auto release = on_scope_exit([&] { destroy_events(fe, 2); });
     if (p->profile) {
         HIP_TRY(hipEventCreate(&fe[0]));
         HIP_TRY(hipEventCreate(&fe[1]));
@@ -1659,8 +1683,6 @@ int hisq_cg_solve_backward(const hisq_geom* g, double mass, int nrhs, const hisq
     if (p->profile) {
         float ms = 0;
         HIP_TRY(hipEventElapsedTime(&ms, fe[0], fe[1]));
-        hipEventDestroy(fe[0]);
-        hipEventDestroy(fe[1]);
         if (info) {
             info->kernel_ms[HISQ_K_FORCE] = ms;
             info->kernel_launches[HISQ_K_FORCE] = 1;
