@@ -257,6 +257,24 @@ def test_headline_mixed_8rhs_true_residual():
         assert res.max() <= 1e-10
 
 
+def test_paper_lattice_64x16_mixed_8rhs_true_residual():
+    """64^3 x 16, the size of the paper's production lattices, m = 0.01,
+    eps = 0.2, 8 rhs, mixed precision with r14 Naik links and autotuned tiles
+    (the benchmark's 64^3 x 16 block): the oracle's FP64 true residual of the
+    returned x is <= 1e-10 for every rhs."""
+    H = gpu_lib()
+    L, m, n = (64, 64, 64, 16), 0.01, 8
+    U, N = W.make_links(L, 0.2, W.links_seed(6))
+    links = H.Links(L, dev(U), dev(N), f32=False, r14=True)
+    b = W.make_sources(L, n, W.sources_seed(6))
+    x, status, info = H.solve(links, m, dev(b), mode=H.MODE_MIXED, naik=H.NAIK_R14)
+    say("64^3 x 16", info["iters"], info["reliable_updates"], info["seconds"])
+    assert status == H.HISQ_OK
+    res = oracle.residual(L, U, N, m, b, host(x))
+    say("oracle true residual", res)
+    assert res.max() <= 1e-10
+
+
 def test_headline_solve_in_the_benchmark_launch_configuration():
     """48^3 x 12, n = 8, m = 0.01, mixed r14 with the tiles bench.py pins: the
     oracle's FP64 true residual of the returned x is <= 1e-10 for every rhs."""
